@@ -1,0 +1,150 @@
+"""Benchmark: exhaustive Gray-code search for the L1 norm of one 42x42 int32 matrix
+(entries uniform in [-100, 100], seed 0; 2^41 sign vectors after the sign symmetry).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+
+One step = one complete L1 solve of the 42x42 matrix on the GPU (result reset,
+sweep kernel, 8-byte result copy), with the matrix tables already resident in HBM.
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit VALU op per lane per clock
+INT32_VALU_PEAK = 256 * 64 * 2.4e9
+METRIC = "Gray-code steps/s (% INT32 VALU peak); 42×42 L1 secs; batched vs plain solves/s"
+
+
+def alg_ops_per_word(kind: str, m: int) -> int:
+    """Irreducible int32 VALU work to score one word: one fused |.|-accumulate per
+    column (per column and message side for L2), plus the running max."""
+    if kind in ("L1", "L_marg"):
+        return m + 1
+    if kind == "L2":
+        return 2 * m + 1
+    raise ValueError(kind)
+
+
+def cpu_baseline(M, target_s: float = 12.0):
+    """The oracle (as it stands) on a bounded sample of the same problem: the
+    sign vectors whose last q = 20 rows take a few fixed prefix values."""
+    import oracle
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+    n = M.shape[0]
+    q = 20
+    words_per_prefix = 2 ** (n - 1 - q)
+    t0 = time.perf_counter()
+    oracle.range_max(M, 1, 0, q, 0, 1, threads)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(64, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.range_max(M, 1, 0, q, 1, 1 + k, threads)
+    dt = time.perf_counter() - t0
+    return {"value": words_per_prefix * k / dt, "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} prefixes x 2^{n - 1 - q} sign vectors of the 42x42 L1 problem "
+                      f"(last {q} rows fixed per prefix), {dt:.1f} s, {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the prefix space would shard across GPUs with one int64 max per problem)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2503_21596_amd as L
+    import synth
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    M = synth.config_42_l1(0)
+    h = L.Prepared(M, 1, 0)
+    plan = h.plan()
+    words = plan["words"]
+
+    for _ in range(a.warmup):
+        h.run(stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kernel_ms = []
+    value = None
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        value = h.run(stream)
+        kernel_ms.append(h.kernel_ms())
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    ms_per_step = total_ms / a.steps
+    steps_per_s = words * a.steps / (total_ms / 1e3)
+    kavg = sum(kernel_ms) / len(kernel_ms)
+    ops = alg_ops_per_word("L1", plan["m"])
+    achieved = words * ops / (kavg / 1e3)
+
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "configs_seed0.json")
+    if os.path.exists(gpath):
+        golden = json.load(open(gpath)).get("values", {}).get("l1_42")
+
+    out = {
+        "metric": METRIC,
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "L1 (local bound) of one 42x42 int32 matrix, entries U[-100,100], seed 0; "
+                               "2^41 Gray-code steps per solve",
+                   "n": 42, "m": 42, "d": 1, "marginals": 0,
+                   "plan": {k: plan[k] for k in ("mp", "R", "C", "P", "n_prefix", "i64")}},
+        "l1_42_seconds": ms_per_step / 1e3,
+        "pct_int32_valu_peak": 100.0 * achieved / INT32_VALU_PEAK,
+        "result": value,
+        "matches_oracle": (value == golden) if golden is not None else None,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
+                     "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_VALU_PEAK,
+                     "traffic": None,
+                     "ops_per_step": ops, "kernel_ms": kavg},
+        "wall_s": wall,
+    }
+
+    if not a.no_extras:
+        Mm = synth.config_42_marg(0)
+        hm = L.Prepared(Mm, 1, 1)
+        vm = hm.run(stream)
+        out["marg_42"] = {"value": vm, "seconds": hm.kernel_ms() / 1e3,
+                          "steps_per_s": hm.plan()["words"] / (hm.kernel_ms() / 1e3)}
+        hm.close()
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(M)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * ld.h -- C ABI of the MI355X (gfx950) L_d-norm library.
+ *
+ * The library computes, by exhaustive Gray-code search on the GPU, the quantities
+ * defined in Marton, Bene, Divianszky, Drotos, arXiv:2503.21596:
+ *
+ *   d = 1, marginals = 0   L1(M)     = max_{a in {+-1}^n} sum_y |sum_x a_x M_xy|
+ *                          the local bound of a correlation Bell expression, Eq. (LM2)
+ *   d = 1, marginals = 1   L_marg(M) = max_{a_0 = +1, a_x = +-1}
+ *                          ( sum_x a_x M_x0 + sum_{y>=1} |sum_x a_x M_xy| ),  Eq. (LMarg)
+ *                          (row 0 and column 0 carry the marginal coefficients)
+ *   d >= 2                 L_d(M)    = max_{a in {0..d-1}^n} sum_k sum_y |sum_{x: a_x=k} M_xy|
+ *                          the classical d-dimensional bound of a prepare-and-measure
+ *                          witness, Eqs. (L_o_norm), (ma).  d = 1 never means this
+ *                          formula (the paper notes Eq. (LM2) is not its d = 1 case).
+ *
+ * Matrices: int32, row-major, M[x*m + y] (x = row, y = column), host memory owned by
+ * the caller, read during the call only (the library copies what it needs).  The
+ * paper requires integer entries; convert real coefficients before calling.
+ *
+ * Values are exact int64.  |value| <= sum |M_xy| < 2^63, so INT64_MIN is never a
+ * value and marks an error; ld_last_error() then gives the code.  L_marg may be
+ * negative (M = [[-5]] gives -5), so no negative number can serve as an error code.
+ *
+ * Thread safety: every entry point may be called from several host threads at
+ * once; each thread uses its own HIP stream and device buffers.
+ */
+#ifndef LD_H
+#define LD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes (0 = success) */
+#define LD_OK 0
+#define LD_EINVAL 1      /* null M, n < 1, m < 1, d < 1, marginals not 0/1, bad range   */
+#define LD_EMARG_D 2     /* marginals with d >= 2: the paper defines them for L1 only   */
+#define LD_ETOOBIG 3     /* search space over 2^62 words after symmetry removal, or a
+                            shape no register-resident kernel covers (see ld_plan)       */
+#define LD_EHIP 4        /* HIP runtime error or no usable gfx950 device                */
+#define LD_EBUSY 5       /* server: arena or queue full, retry later                     */
+#define LD_PENDING 6     /* server: result not ready yet                                  */
+#define LD_ENOTFOUND 7   /* server: unknown ticket                                        */
+
+/* ld_norm -- L1 / L_marg / L_d of one matrix (definitions above).
+ * Preprocessing keeps the value exactly: all-zero rows and columns are dropped
+ * (Sec. 2.1.1, 2.2, 2.3.1), L1 and L_marg are computed on the transpose when
+ * n > m (Sec. 2.1.1; for L_marg the marginal row and column swap roles), and
+ * for d >= 2 with d >= (remaining rows) the value is sum |M_xy|.
+ * Synchronous: returns after the result is on the host.
+ * Returns the value, or INT64_MIN with ld_last_error() set. */
+int64_t ld_norm(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals);
+
+/* One problem of a batch. */
+typedef struct {
+    const int32_t* M;     /* host, row-major n x m, caller-owned */
+    int32_t n, m, d, marginals;
+} ld_problem;
+
+/* ld_norm_batch -- many independent problems in one persistent launch.
+ * out[i] receives problem i's value, or INT64_MIN on error; status (nullable)
+ * receives each problem's error code.  hip_stream: a hipStream_t, or NULL for
+ * the library's own stream; with a caller stream the call still returns after
+ * the results are in out[].  Returns LD_OK, or the first error code met. */
+int ld_norm_batch(const ld_problem* probs, int32_t count, int64_t* out, int32_t* status,
+                  void* hip_stream);
+
+/* ld_norm_range -- the maximum over part of the search space, for spot checks
+ * at full size.  No preprocessing.  Row 0 is fixed (a_0 = +1 for d = 1, message
+ * 0 for d >= 2), the last q rows are set by a prefix value p in
+ * [prefix_begin, prefix_end): for d = 1 bit i of p is 1 when a_{n-q+i} = +1; for
+ * d >= 2 digit i (base d) of p is the message of row n-q+i.  Rows 1 .. n-q-1
+ * are free.  Returns INT64_MIN on error (empty range: LD_EINVAL). */
+int64_t ld_norm_range(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
+                      int32_t q, uint64_t prefix_begin, uint64_t prefix_end);
+
+/* How a problem is laid out for the sweep.  kind: 0 L1, 1 L_marg, 2 L2, 3 L_d
+ * (d >= 3), 4 sum|M| (d >= rows), 5 constant zero (empty after preprocessing). */
+typedef struct {
+    int32_t kind;
+    int32_t n, m, d;      /* after preprocessing */
+    int32_t transposed;
+    int32_t i64;          /* 1: int64 path (sum |M_xy| >= 2^31) */
+    int32_t mp;           /* padded column count of the kernel instantiation */
+    int32_t R, C, P;      /* low (patterns per state), mid (Gray), high (prefix) rows */
+    int32_t P_tab;        /* d-ary rows covered by restricted-growth prefixes */
+    uint64_t n_prefix;    /* prefixes, i.e. lane-sized work units */
+    double words;         /* assignments scored */
+} ld_plan_info;
+
+/* ---------------------------------------------------------------------------
+ * Prepared problems: plan once, keep the tables resident in HBM, run many times.
+ * ld_prepare plans M as ld_norm does and copies its tables to the current
+ * device (synchronously); M is not retained.  Returns NULL on error.
+ * ld_run enqueues the sweep on hip_stream (a hipStream_t, or NULL for a stream
+ * owned by the handle), copies the 8-byte result back and waits for it.
+ * The sweep kernel is bracketed by two HIP events on that stream;
+ * ld_last_kernel_ms gives the time between them for the last ld_run.
+ * A handle is used by one thread at a time; ld_release frees it. */
+typedef struct ld_prepared ld_prepared;
+ld_prepared* ld_prepare(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals);
+int ld_run(ld_prepared* h, void* hip_stream, int64_t* value);
+float ld_last_kernel_ms(ld_prepared* h);
+int ld_prepared_plan(const ld_prepared* h, ld_plan_info* info);
+void ld_release(ld_prepared* h);
+
+/* Error code of the calling thread's last failed call, and its text. */
+int ld_last_error(void);
+const char* ld_error_string(int code);
+
+/* ---------------------------------------------------------------------------
+ * Introspection (host only, never touches the GPU). */
+
+
+/* Plan a problem as ld_norm would.  Returns LD_OK or an error code. */
+int ld_plan(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
+            ld_plan_info* info);
+
+/* Gray-code digits as the kernels compute them (Sec. 2.1.2, 2.3.2).
+ * ld_gray_digit: digit i of word j of the d-ary reflected Gray code (d = 2: the
+ * binary reflected code, Eq. (Hamming_equation)).
+ * ld_gray_change: for word j >= 1, the digit that differs from word j - 1
+ * (Eqs. (Hamming_equation_change), (d_aryGrayChange_1)) and its old / new value. */
+uint32_t ld_gray_digit(uint32_t d, uint32_t i, uint64_t j);
+int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
+
+/* Sweep shape used for new plans (0 = keep).  p_target: high rows (lanes =
+ * 2^p_target) for large binary problems; c_min: least mid rows per lane;
+ * r_drop: 1 to score one low row fewer per state than the register budget allows;
+ * dary_ptab: rows covered by restricted-growth prefixes (<= 16). */
+void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LD_H */

@@ -223,23 +223,35 @@ typedef struct {
     int64_t best;
 } split_job_t;
 
+/* Every pair (p, q) is scored exactly once.  The pairs are visited tile by tile
+ * (TILE_Q values of q against TILE_P values of p) so that the rows of both
+ * tables in use stay in cache; the order of a maximum does not matter. */
+#define TILE_P 512
+#define TILE_Q 64
+
 static void* split_worker(void* arg)
 {
     split_job_t* j = (split_job_t*)arg;
     const int m = j->m;
     int64_t best = INT64_MIN;
-    for (uint64_t q = j->nb_lo; q < j->nb_hi; ++q) {
-        const int64_t* tb = j->TB + q * (uint64_t)m;
-        for (uint64_t p = 0; p < j->na; ++p) {
-            const int64_t* ta = j->TA + p * (uint64_t)m;
-            int64_t total = 0;
-            if (j->marg) {
-                total = ta[0] + tb[0];
-                for (int y = 1; y < m; ++y) total += iabs64(ta[y] + tb[y]);
-            } else {
-                for (int y = 0; y < m; ++y) total += iabs64(ta[y] + tb[y]);
+    for (uint64_t q0 = j->nb_lo; q0 < j->nb_hi; q0 += TILE_Q) {
+        const uint64_t q1 = q0 + TILE_Q < j->nb_hi ? q0 + TILE_Q : j->nb_hi;
+        for (uint64_t p0 = 0; p0 < j->na; p0 += TILE_P) {
+            const uint64_t p1 = p0 + TILE_P < j->na ? p0 + TILE_P : j->na;
+            for (uint64_t q = q0; q < q1; ++q) {
+                const int64_t* tb = j->TB + q * (uint64_t)m;
+                for (uint64_t p = p0; p < p1; ++p) {
+                    const int64_t* ta = j->TA + p * (uint64_t)m;
+                    int64_t total = 0;
+                    if (j->marg) {
+                        total = ta[0] + tb[0];
+                        for (int y = 1; y < m; ++y) total += iabs64(ta[y] + tb[y]);
+                    } else {
+                        for (int y = 0; y < m; ++y) total += iabs64(ta[y] + tb[y]);
+                    }
+                    if (total > best) best = total;
+                }
             }
-            if (total > best) best = total;
         }
     }
     j->best = best;

@@ -1,0 +1,101 @@
+// Binary-kind sweep kernels (L1, L_marg, L2) for one kind, selected by LD_KIND at
+// compile time so the three kinds build as separate objects in parallel.
+#include <hip/hip_runtime.h>
+#include <utility>
+
+#include "ld_registry.h"
+#include "ld_sweep.h"
+
+#ifndef LD_KIND
+#error "LD_KIND must be 0 (L1), 1 (L_marg) or 2 (L2)"
+#endif
+
+namespace ld {
+
+// One launch covers prefixes [0, n_prefix) of one problem; lane l takes prefixes
+// l, l + T, l + 2T, ... (T = grid size in lanes).  Lanes past the end repeat the
+// last prefix, which cannot change a maximum, so every wave stays converged.
+template <int MP, int KIND, int R>
+__global__ __launch_bounds__(256) void k_bin32(Desc D)
+{
+    using B = Bin32<MP, KIND, R>;
+    uint32_t off[B::K][B::NW][MP];
+    B::load_offs(D, off);
+    uint32_t best = B::best_init();
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
+    for (uint64_t j = 0; j < rounds; ++j) {
+        uint64_t p = lane + j * nth;
+        if (p >= D.n_prefix) p = D.n_prefix - 1;
+        B::prefix(D, D.pfx_base + p, off, best);
+    }
+    publish(D.result, B::finish(best));
+}
+
+template <int MP, int KIND>
+__global__ __launch_bounds__(256) void k_bin64(Desc D)
+{
+    using B = Bin64<MP, KIND>;
+    int64_t best = B::best_init();
+    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
+    for (uint64_t j = 0; j < rounds; ++j) {
+        uint64_t p = lane + j * nth;
+        if (p >= D.n_prefix) p = D.n_prefix - 1;
+        B::prefix(D, D.pfx_base + p, best);
+    }
+    publish(D.result, B::finish(best));
+}
+
+namespace {
+
+constexpr int NMP = MAX_MP / 2;   // mp = 2, 4, ..., 64
+const void* g_bin32[NMP][MAX_R + 1] = {};
+const void* g_bin64[MAX_MP / 8] = {};
+
+template <int MP, int R>
+void reg_one()
+{
+    if constexpr (R >= 0) g_bin32[MP / 2 - 1][R] = (const void*)&k_bin32<MP, LD_KIND, R>;
+}
+
+template <int MP>
+void reg_mp()
+{
+    constexpr int rmax = bin_rmax(MP, LD_KIND);
+    // the two largest R values that fit: the tuner chooses between them
+    reg_one<MP, rmax>();
+    if constexpr (rmax >= 1) reg_one<MP, rmax - 1>();
+    if constexpr (MP % 8 == 0) g_bin64[MP / 8 - 1] = (const void*)&k_bin64<MP, LD_KIND>;
+}
+
+template <int... I>
+void reg_all(std::integer_sequence<int, I...>)
+{
+    (reg_mp<2 * (I + 1)>(), ...);
+}
+
+struct Init {
+    Init() { reg_all(std::make_integer_sequence<int, NMP>{}); }
+} g_init;
+
+}  // namespace
+
+#define LD_CAT2(a, b) a##b
+#define LD_CAT(a, b) LD_CAT2(a, b)
+
+const void* LD_CAT(lookup_bin32_kind, LD_KIND)(int mp, int R)
+{
+    if (mp < 2 || mp > MAX_MP || (mp & 1) || R < 0 || R > MAX_R) return nullptr;
+    return g_bin32[mp / 2 - 1][R];
+}
+
+const void* LD_CAT(lookup_bin64_kind, LD_KIND)(int mp)
+{
+    if (mp < 8 || mp > MAX_MP || (mp & 7)) return nullptr;
+    return g_bin64[mp / 8 - 1];
+}
+
+}  // namespace ld

@@ -1,0 +1,572 @@
+// Host planner (see ld_plan.h).
+#include "ld_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "ld.h"
+#include "ld_registry.h"
+
+namespace ld {
+
+namespace {
+
+std::mutex g_shape_mu;
+SweepShape g_shape;
+
+struct Mat {
+    int n = 0, m = 0;
+    std::vector<int32_t> a;
+    int32_t at(int x, int y) const { return a[(size_t)x * m + y]; }
+};
+
+Mat transpose(const Mat& A)
+{
+    Mat T;
+    T.n = A.m;
+    T.m = A.n;
+    T.a.resize(A.a.size());
+    for (int x = 0; x < A.n; ++x)
+        for (int y = 0; y < A.m; ++y) T.a[(size_t)y * T.m + x] = A.at(x, y);
+    return T;
+}
+
+bool row_zero(const Mat& A, int x)
+{
+    for (int y = 0; y < A.m; ++y)
+        if (A.at(x, y)) return false;
+    return true;
+}
+
+bool col_zero(const Mat& A, int y)
+{
+    for (int x = 0; x < A.n; ++x)
+        if (A.at(x, y)) return false;
+    return true;
+}
+
+// Drop all-zero rows and columns; rows / columns with index 0 are kept when
+// keep0 is set (the marginal row and column of Eq. (LMarg)).
+Mat drop_zeros(const Mat& A, bool keep0)
+{
+    std::vector<int> rows, cols;
+    for (int x = 0; x < A.n; ++x)
+        if ((keep0 && x == 0) || !row_zero(A, x)) rows.push_back(x);
+    for (int y = 0; y < A.m; ++y)
+        if ((keep0 && y == 0) || !col_zero(A, y)) cols.push_back(y);
+    Mat B;
+    B.n = (int)rows.size();
+    B.m = (int)cols.size();
+    B.a.resize((size_t)B.n * B.m);
+    for (int i = 0; i < B.n; ++i)
+        for (int j = 0; j < B.m; ++j) B.a[(size_t)i * B.m + j] = A.at(rows[i], cols[j]);
+    return B;
+}
+
+Mat drop_first_row_col(const Mat& A)
+{
+    Mat B;
+    B.n = A.n - 1;
+    B.m = A.m - 1;
+    B.a.resize((size_t)std::max(0, B.n) * std::max(0, B.m));
+    for (int x = 1; x < A.n; ++x)
+        for (int y = 1; y < A.m; ++y) B.a[(size_t)(x - 1) * B.m + (y - 1)] = A.at(x, y);
+    return B;
+}
+
+int64_t sum_abs(const Mat& A)
+{
+    int64_t s = 0;
+    for (int32_t v : A.a) s += v < 0 ? -(int64_t)v : (int64_t)v;
+    return s;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+template <class T>
+void put(std::vector<uint8_t>& blob, size_t off, size_t idx, T v)
+{
+    std::memcpy(blob.data() + off + sizeof(T) * idx, &v, sizeof(T));
+}
+
+constexpr int64_t BIAS = (int64_t)1 << 31;
+constexpr uint64_t WORD_LIMIT = (uint64_t)1 << 62;
+
+// Binary tables.  Row roles in A: row 0 fixed (a_0 = +1, or message 0 for L2),
+// rows 1..R low, then C mid rows, then P high rows.  A digit is the bit of the
+// Gray word / prefix / low pattern:
+//   L1 / L_marg: digit 1 -> a = +1 (contributes +M_x), digit 0 -> a = -1 (-M_x)
+//   L2: the digit is the message; the state is the sum of the rows sent as
+//       message 0 (the fixed row and every digit-0 row)
+void build_binary(Plan& p, const Mat& A)
+{
+    const bool l2 = (p.kind == PK_L2);
+    const int m = A.m, mp = p.mp, R = p.R, C = p.C, P = p.P;
+    const int NW = 1 << R;
+    auto v0 = [&](int x, int y) -> int64_t { return l2 ? (int64_t)A.at(x, y) : -(int64_t)A.at(x, y); };
+    auto v1 = [&](int x, int y) -> int64_t { return l2 ? 0 : (int64_t)A.at(x, y); };
+    const int mid0 = 1 + R, high0 = 1 + R + C;
+
+    std::vector<int64_t> base(mp, 0), total(mp, 0);
+    for (int y = 0; y < m; ++y) {
+        int64_t b = A.at(0, y);
+        for (int x = mid0; x < high0 + P; ++x) b += v0(x, y);
+        base[y] = b;
+        for (int x = 0; x < A.n; ++x) total[y] += A.at(x, y);
+    }
+    auto delta = [&](int x, int y) -> int64_t { return y < m ? v1(x, y) - v0(x, y) : 0; };
+
+    if (!p.i64) {
+        const int RS = (mp + 15) & ~15;
+        const int K = l2 ? 2 : 1;
+        p.off_base = 0;
+        p.off_hid = align256(p.off_base + 4 * (size_t)mp);
+        p.off_mid = align256(p.off_hid + 4 * (size_t)std::max(P, 1) * RS);
+        p.off_offs = align256(p.off_mid + 4 * (size_t)std::max(C, 1) * 2 * RS);
+        p.off_tab = align256(p.off_offs + 4 * (size_t)K * NW * mp);
+        p.blob.assign(p.off_tab, 0);
+        for (int y = 0; y < mp; ++y) put<uint32_t>(p.blob, p.off_base, y, (uint32_t)(base[y] + BIAS));
+        for (int h = 0; h < P; ++h)
+            for (int y = 0; y < mp; ++y)
+                put<int32_t>(p.blob, p.off_hid, (size_t)h * RS + y, (int32_t)(uint32_t)delta(high0 + h, y));
+        for (int k = 0; k < C; ++k)
+            for (int y = 0; y < mp; ++y) {
+                const int64_t dv = delta(mid0 + k, y);
+                put<int32_t>(p.blob, p.off_mid, (size_t)(2 * k) * RS + y, (int32_t)(uint32_t)dv);
+                put<int32_t>(p.blob, p.off_mid, (size_t)(2 * k + 1) * RS + y, (int32_t)(uint32_t)(-dv));
+            }
+        for (int w = 0; w < NW; ++w)
+            for (int y = 0; y < mp; ++y) {
+                int64_t low = 0;
+                if (y < m)
+                    for (int i = 0; i < R; ++i) low += ((w >> i) & 1) ? v1(1 + i, y) : v0(1 + i, y);
+                // |s - o| with s = true + 2^31 must equal |true + low| (and for L2
+                // the second operand gives |total - (true + low)|)
+                put<uint32_t>(p.blob, p.off_offs, (size_t)w * mp + y, (uint32_t)(BIAS - low));
+                if (l2)
+                    put<uint32_t>(p.blob, p.off_offs, (size_t)(NW + w) * mp + y,
+                                  (uint32_t)(BIAS + total[y] - low));
+            }
+    } else {
+        p.off_base = 0;
+        p.off_hid = align256(p.off_base + 8 * (size_t)mp);
+        p.off_mid = align256(p.off_hid + 8 * (size_t)std::max(P, 1) * mp);
+        p.off_offs = align256(p.off_mid + 8 * (size_t)std::max(C, 1) * 2 * mp);
+        p.off_tab = align256(p.off_offs + 8 * (size_t)mp);
+        p.blob.assign(p.off_tab, 0);
+        for (int y = 0; y < mp; ++y) put<int64_t>(p.blob, p.off_base, y, base[y]);
+        for (int h = 0; h < P; ++h)
+            for (int y = 0; y < mp; ++y) put<int64_t>(p.blob, p.off_hid, (size_t)h * mp + y, delta(high0 + h, y));
+        for (int k = 0; k < C; ++k)
+            for (int y = 0; y < mp; ++y) {
+                put<int64_t>(p.blob, p.off_mid, (size_t)(2 * k) * mp + y, delta(mid0 + k, y));
+                put<int64_t>(p.blob, p.off_mid, (size_t)(2 * k + 1) * mp + y, -delta(mid0 + k, y));
+            }
+        for (int y = 0; y < mp; ++y) put<int64_t>(p.blob, p.off_offs, y, total[y]);
+    }
+}
+
+// d-ary tables.  Row roles in A: P_tab prefix rows covered by tab[], then P
+// plain prefix rows, then C mid rows; `fixed0`: row 0 is fixed at message 0
+// instead (range plans), the remaining rows follow it.
+void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fixed0)
+{
+    const int m = A.m, mp = p.mp, C = p.C;
+    const int nh = p.P_tab + p.P;
+    const int h0 = fixed0 ? 1 : 0;          // first prefix row
+    const int mid0 = h0 + nh;
+    const size_t es = p.i64 ? 8 : 4;
+    p.off_base = 0;
+    p.off_hid = align256(es * (size_t)mp);
+    p.off_mid = align256(p.off_hid + es * (size_t)std::max(nh, 1) * mp);
+    p.off_tab = align256(p.off_mid + es * (size_t)std::max(C, 1) * mp);
+    p.off_offs = p.off_tab;
+    const size_t end = align256(p.off_tab + 8 * std::max<size_t>(tab.size(), 1));
+    p.blob.assign(end, 0);
+    for (int y = 0; y < mp; ++y) {
+        int64_t b = 0;
+        if (y < m) {
+            if (fixed0) b += A.at(0, y);
+            for (int c = 0; c < C; ++c) b += A.at(mid0 + c, y);
+        }
+        if (p.i64) put<int64_t>(p.blob, p.off_base, y, b);
+        else put<uint32_t>(p.blob, p.off_base, y, (uint32_t)(b + BIAS));
+    }
+    auto row = [&](size_t off, int slot, int x) {
+        for (int y = 0; y < mp; ++y) {
+            const int64_t v = y < m ? A.at(x, y) : 0;
+            if (p.i64) put<int64_t>(p.blob, off, (size_t)slot * mp + y, v);
+            else put<int32_t>(p.blob, off, (size_t)slot * mp + y, (int32_t)v);
+        }
+    };
+    for (int h = 0; h < nh; ++h) row(p.off_hid, h, h0 + h);
+    for (int c = 0; c < C; ++c) row(p.off_mid, c, mid0 + c);
+    for (size_t i = 0; i < tab.size(); ++i) put<uint64_t>(p.blob, p.off_tab, i, tab[i]);
+}
+
+// All restricted-growth strings of length L over {0..d-1}: s_0 = 0 and each
+// s_i at most one above the largest earlier digit.  Every assignment of rows to
+// messages can be relabelled (a permutation of the messages, which keeps the
+// witness value of Eq. (L_o_norm)) so that its first L digits form such a string.
+void rgs(int L, int d, std::vector<uint64_t>& out)
+{
+    if (L <= 0) {
+        out.push_back(0);
+        return;
+    }
+    struct Frame { int i, mx; uint64_t code; };
+    std::vector<Frame> st;
+    st.push_back({1, 0, 0});
+    while (!st.empty()) {
+        Frame f = st.back();
+        st.pop_back();
+        if (f.i == L) {
+            out.push_back(f.code);
+            continue;
+        }
+        const int top = std::min(f.mx + 1, d - 1);
+        for (int v = top; v >= 0; --v)
+            st.push_back({f.i + 1, std::max(f.mx, v), f.code | ((uint64_t)v << (4 * f.i))});
+    }
+}
+
+// number of restricted-growth strings of length L with at most d distinct digits
+// (sum over k <= d of the Stirling numbers of the second kind S(L, k))
+double rgs_count(int L, int d)
+{
+    std::vector<double> S(d + 1, 0.0);   // S[k] for the current length
+    S[0] = 1.0;                          // length 0
+    for (int n = 1; n <= L; ++n)
+        for (int k = std::min(n, d); k >= 1; --k) S[k] = k * S[k] + S[k - 1];
+    double t = 0;
+    for (int k = 1; k <= d; ++k) t += S[k];
+    return L == 0 ? 1.0 : t;
+}
+
+uint64_t upow(uint64_t b, int e, bool* overflow)
+{
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) {
+        if (r > WORD_LIMIT / b) *overflow = true;
+        r *= b;
+    }
+    return r;
+}
+
+void choose_binary_shape(Plan& p, const SweepShape& sh, int F)
+{
+    // F free rows beyond the R low rows
+    const int Fp = F - p.R;
+    int P = std::min(Fp, sh.p_target);
+    int C = Fp - P;
+    if (C < sh.c_min) {
+        C = std::min(Fp, sh.c_min);
+        P = Fp - C;
+    }
+    if (C > 31) {
+        C = 31;
+        P = Fp - 31;
+    }
+    p.C = C;
+    p.P = P;
+    p.n_prefix = (uint64_t)1 << P;
+}
+
+// The wide kernel: int64 tables with row stride m, state in LDS.
+bool use_wide(Plan& p, int states)
+{
+    p.wide = 1;
+    p.i64 = 1;
+    p.mp = p.m;
+    p.lds = 8 * ((size_t)states * p.m + (size_t)states);
+    p.kernel = kernel_wide();
+    return p.lds <= WIDE_LDS_MAX;
+}
+
+Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
+{
+    // A: row 0 fixed; p.kind set; p.i64 set
+    if (A.n - 1 > 62) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    p.mp = p.i64 ? pad_bin64(A.m) : pad_bin32(A.m);
+    p.kernel = nullptr;
+    if (A.m <= MAX_MP && p.mp <= MAX_MP) {
+        if (p.i64) {
+            p.R = 0;
+        } else {
+            const int rmax = bin_rmax(p.mp, p.kind);
+            p.R = std::max(0, rmax - (sh.r_drop ? 1 : 0));
+        }
+        p.kernel = p.i64 ? kernel_bin64(p.kind, p.mp) : kernel_bin32(p.kind, p.mp, p.R);
+    }
+    if (!p.kernel) {
+        p.R = 0;
+        if (!use_wide(p, 1)) {
+            p.status = LD_ETOOBIG;
+            return p;
+        }
+    }
+    // too few free rows for R low patterns: append all-zero rows (they change no
+    // column sum, so the maximum is unchanged; only words are repeated)
+    while (A.n - 1 < p.R) {
+        A.a.resize((size_t)(A.n + 1) * A.m, 0);
+        A.n += 1;
+    }
+    choose_binary_shape(p, sh, A.n - 1);
+    if (p.wide && p.C > 40) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    p.words = (double)((uint64_t)1 << (A.n - 1));
+    build_binary(p, A);
+    return p;
+}
+
+}  // namespace
+
+SweepShape get_shape()
+{
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    return g_shape;
+}
+
+void set_shape(const SweepShape& s)
+{
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    g_shape = s;
+}
+
+Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const SweepShape& sh)
+{
+    Plan p;
+    if (!M || n < 1 || m < 1 || d < 1 || (marginals != 0 && marginals != 1)) {
+        p.status = LD_EINVAL;
+        return p;
+    }
+    if (marginals && d >= 2) {
+        p.status = LD_EMARG_D;
+        return p;
+    }
+    Mat A;
+    A.n = n;
+    A.m = m;
+    A.a.assign(M, M + (size_t)n * m);
+    p.d = d;
+
+    if (d == 1 && marginals) {
+        A = drop_zeros(A, true);
+        if (row_zero(A, 0) && col_zero(A, 0)) {
+            // no marginals at all: L_marg is L1 of the correlation block (Sec. 2.2)
+            A = drop_first_row_col(A);
+            A = drop_zeros(A, false);
+            p.kind = PK_L1;
+        } else {
+            p.kind = PK_MARG;
+        }
+    } else {
+        A = drop_zeros(A, false);
+        p.kind = d == 1 ? PK_L1 : (d == 2 ? PK_L2 : PK_LD);
+    }
+    if (A.n == 0 || A.m == 0) {
+        p.kind = PK_ZERO;
+        p.n = p.m = 0;
+        return p;
+    }
+    if ((p.kind == PK_L1 || p.kind == PK_MARG) && A.n > A.m) {
+        A = transpose(A);   // L1(M) = L1(M^T); L_marg too (row 0 <-> column 0)
+        p.transposed = 1;
+    }
+    if (p.kind == PK_L2 || p.kind == PK_LD) {
+        if (d >= A.n) {
+            p.kind = PK_SUMABS;   // every row can take its own message
+        }
+    }
+    p.n = A.n;
+    p.m = A.m;
+    p.d = std::min(d, A.n);
+    const int64_t B = sum_abs(A);
+    p.i64 = B > (int64_t)0x7fffffff ? 1 : 0;
+
+    if (p.kind == PK_SUMABS) {
+        p.M = A.a;
+        p.blob.resize(align256(4 * A.a.size()));
+        std::memcpy(p.blob.data(), A.a.data(), 4 * A.a.size());
+        p.words = 1;
+        return p;
+    }
+    if (p.kind != PK_LD) {
+        p.M = A.a;
+        return finish_binary(p, A, sh);
+    }
+
+    // d >= 3, d < n
+    p.mp = pad_dary(A.m);
+    p.kernel = nullptr;
+    if (A.m <= MAX_MP && d <= MAX_D)
+        p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
+    if (!p.kernel && !use_wide(p, d)) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
+    // row is fixed (message 0), which is the paper's fix-one-entry reduction
+    p.P_tab = d <= 16 ? std::min(A.n, std::max(1, std::min(16, sh.dary_ptab))) : 1;
+    while (p.P_tab > 1 && rgs_count(p.P_tab, d) > (double)(1 << 20)) --p.P_tab;
+    const int rest = A.n - p.P_tab;
+    int C = 0;
+    {
+        uint64_t w = 1;
+        while (C < rest && w * (uint64_t)d <= (uint64_t)std::max(1, sh.dary_cwords)) {
+            w *= d;
+            ++C;
+        }
+    }
+    p.C = C;
+    p.P = rest - C;
+    std::vector<uint64_t> tab;
+    rgs(p.P_tab, d, tab);
+    bool of = false;
+    p.dpow_free = upow(d, p.P, &of);
+    const uint64_t cw = upow(d, C, &of);
+    if (of || (double)tab.size() * (double)p.dpow_free * (double)cw > (double)WORD_LIMIT) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    p.n_prefix = (uint64_t)tab.size() * p.dpow_free;
+    p.words = (double)p.n_prefix * (double)cw;
+    p.M = A.a;
+    build_dary(p, A, tab, false);
+    return p;
+}
+
+Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q,
+                     uint64_t pfx_begin, uint64_t pfx_end)
+{
+    Plan p;
+    if (!M || n < 1 || m < 1 || d < 1 || (marginals != 0 && marginals != 1) || q < 0 || q > n - 1 ||
+        pfx_begin >= pfx_end) {
+        p.status = LD_EINVAL;
+        return p;
+    }
+    if (marginals && d >= 2) {
+        p.status = LD_EMARG_D;
+        return p;
+    }
+    const int radix = d == 1 ? 2 : d;
+    bool of = false;
+    const uint64_t npfx = upow(radix, q, &of);
+    if (of || pfx_end > npfx) {
+        p.status = of ? LD_ETOOBIG : LD_EINVAL;
+        return p;
+    }
+    Mat A;
+    A.n = n;
+    A.m = m;
+    A.a.assign(M, M + (size_t)n * m);
+    p.n = n;
+    p.m = m;
+    p.d = d;
+    p.kind = d == 1 ? (marginals ? PK_MARG : PK_L1) : (d == 2 ? PK_L2 : PK_LD);
+    p.i64 = sum_abs(A) > (int64_t)0x7fffffff ? 1 : 0;
+    p.pfx_base = pfx_begin;
+    p.n_prefix = pfx_end - pfx_begin;
+    p.M = A.a;
+    const int free_rows = n - 1 - q;   // rows 1 .. n-q-1
+
+    if (p.kind != PK_LD) {
+        p.mp = p.i64 ? pad_bin64(m) : pad_bin32(m);
+        p.R = p.i64 ? 0 : bin_rmax(p.mp, p.kind);
+        p.kernel = nullptr;
+        if (m <= MAX_MP && p.mp <= MAX_MP)
+            p.kernel = p.i64 ? kernel_bin64(p.kind, p.mp) : kernel_bin32(p.kind, p.mp, p.R);
+        if (!p.kernel) {
+            p.R = 0;
+            if (!use_wide(p, 1)) {
+                p.status = LD_ETOOBIG;
+                return p;
+            }
+        }
+        // rows: 0 fixed, then R low + C mid taken from rows 1..n-q-1 (padded with
+        // zero rows when there are fewer than R), then the q prefix rows in order
+        Mat B;
+        const int lowmid = std::max(free_rows, p.R);
+        B.n = 1 + lowmid + q;
+        B.m = m;
+        B.a.assign((size_t)B.n * m, 0);
+        for (int y = 0; y < m; ++y) B.a[y] = A.at(0, y);
+        for (int x = 1; x <= free_rows; ++x)
+            for (int y = 0; y < m; ++y) B.a[(size_t)x * m + y] = A.at(x, y);
+        for (int i = 0; i < q; ++i)
+            for (int y = 0; y < m; ++y) B.a[(size_t)(1 + lowmid + i) * m + y] = A.at(n - q + i, y);
+        p.C = lowmid - p.R;
+        p.P = q;
+        if (p.C > 31) {
+            p.status = LD_ETOOBIG;
+            return p;
+        }
+        p.words = (double)p.n_prefix * (double)((uint64_t)1 << lowmid);
+        build_binary(p, B);
+        return p;
+    }
+
+    // d >= 3: row 0 fixed at message 0; rows 1..n-q-1 mid; the last q rows prefix
+    p.mp = pad_dary(m);
+    p.kernel = nullptr;
+    if (m <= MAX_MP && d <= MAX_D) p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
+    if (!p.kernel && !use_wide(p, d)) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    const uint64_t cw = upow(d, free_rows, &of);
+    if (of || cw > 0xffffffffull) {
+        p.status = LD_ETOOBIG;
+        return p;
+    }
+    p.P_tab = 0;
+    p.P = q;
+    p.C = free_rows;
+    p.dpow_free = npfx;
+    p.words = (double)p.n_prefix * (double)cw;
+    // B: row 0, then the q prefix rows, then the mid rows
+    Mat B;
+    B.n = n;
+    B.m = m;
+    B.a.assign((size_t)n * m, 0);
+    for (int y = 0; y < m; ++y) B.a[y] = A.at(0, y);
+    for (int i = 0; i < q; ++i)
+        for (int y = 0; y < m; ++y) B.a[(size_t)(1 + i) * m + y] = A.at(n - q + i, y);
+    for (int c = 0; c < free_rows; ++c)
+        for (int y = 0; y < m; ++y) B.a[(size_t)(1 + q + c) * m + y] = A.at(1 + c, y);
+    build_dary(p, B, {}, true);
+    return p;
+}
+
+Desc make_desc(const Plan& p, const void* dev_blob, int64_t* result)
+{
+    Desc D{};
+    D.kind = p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
+    D.m = p.m;
+    D.mp = p.mp;
+    D.d = p.d;
+    D.i64 = p.i64;
+    D.R = p.R;
+    D.C = p.C;
+    D.P = p.P;
+    D.P_tab = p.P_tab;
+    D.pfx_base = p.pfx_base;
+    D.n_prefix = p.n_prefix;
+    D.dpow_free = p.dpow_free;
+    const uint8_t* b = (const uint8_t*)dev_blob;
+    D.base = b + p.off_base;
+    D.hid = b + p.off_hid;
+    D.mid = b + p.off_mid;
+    D.offs = b + p.off_offs;
+    D.tab = (const uint64_t*)(b + p.off_tab);
+    D.result = result;
+    return D;
+}
+
+}  // namespace ld

@@ -1,0 +1,55 @@
+// Host planner: validation, value-preserving preprocessing, the row roles of the
+// sweep and the device tables of one problem.
+#pragma once
+#include <stdint.h>
+#include <vector>
+
+#include "ld_types.h"
+
+namespace ld {
+
+enum PlanKind : int32_t { PK_L1 = 0, PK_MARG = 1, PK_L2 = 2, PK_LD = 3, PK_SUMABS = 4, PK_ZERO = 5 };
+
+struct SweepShape {
+    int p_target = 20;   // high rows of a large binary problem (2^20 lanes)
+    int c_min = 4;       // least mid rows per lane when the problem allows it
+    int r_drop = 0;      // 1: one low row fewer than the register budget allows
+    int dary_ptab = 8;   // restricted-growth prefix rows for d >= 3
+    int dary_cwords = 4096;  // target d^C words per lane for d >= 3
+};
+
+struct Plan {
+    int status = 0;            // LD_OK or an error code
+    int kind = PK_ZERO;
+    int n = 0, m = 0, d = 1;   // after preprocessing
+    int transposed = 0;
+    int i64 = 0;
+    int mp = 0;
+    int R = 0, C = 0, P = 0, P_tab = 0;
+    uint64_t n_prefix = 0;
+    uint64_t pfx_base = 0;
+    uint64_t dpow_free = 1;
+    double words = 0;
+    std::vector<int32_t> M;    // preprocessed matrix, n x m
+    // device tables, laid out in one blob; offsets in bytes, each 256-aligned
+    std::vector<uint8_t> blob;
+    size_t off_base = 0, off_hid = 0, off_mid = 0, off_offs = 0, off_tab = 0;
+    const void* kernel = nullptr;  // sweep kernel, null for PK_ZERO / PK_SUMABS
+    int wide = 0;                  // 1: the wide (LDS-state, one wave per prefix) kernel
+    size_t lds = 0;                // dynamic LDS bytes of the wide kernel
+};
+
+SweepShape get_shape();
+void set_shape(const SweepShape& s);
+
+// Full problem as ld_norm sees it.
+Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const SweepShape& shape);
+
+// Prefix-range problem as ld_norm_range sees it (no preprocessing).
+Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q,
+                     uint64_t pfx_begin, uint64_t pfx_end);
+
+// Fill the pointer fields of a descriptor for a blob placed at device address dev.
+Desc make_desc(const Plan& p, const void* dev_blob, int64_t* result);
+
+}  // namespace ld

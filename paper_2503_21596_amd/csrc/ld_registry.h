@@ -1,0 +1,50 @@
+// Host-side table of the sweep kernel instantiations.
+//
+// Every instantiation is fixed at compile time by its padded column count MP and
+// (binary kinds) the number of low rows R scored per state, or (d-ary) the
+// alphabet size d, so that the column-sum vectors live entirely in VGPRs.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ld {
+
+// VGPR budget for the register-resident state of one lane: the state vector(s)
+// plus the low-row operands must fit in 224 registers so that two waves fit on a
+// SIMD (512 VGPRs per lane slot) with room for temporaries.
+constexpr int VGPR_STATE_BUDGET = 224;
+constexpr int MAX_R = 3;
+
+constexpr int bin_k(int kind) { return kind == 2 ? 2 : 1; }
+
+// largest R <= MAX_R with (1 + K * 2^R) * mp <= budget, or -1 if even R = 0 fails
+constexpr int bin_rmax(int mp, int kind)
+{
+    for (int r = MAX_R; r >= 0; --r)
+        if ((1 + bin_k(kind) * (1 << r)) * mp <= VGPR_STATE_BUDGET) return r;
+    return -1;
+}
+
+// d-ary: d vectors of mp columns
+constexpr bool dary_fits(int mp, int d) { return d * mp <= 192; }
+
+struct KernelRef {
+    const void* fn = nullptr;   // __global__ function
+};
+
+// lookups; return nullptr when no instantiation exists
+const void* kernel_bin32(int kind, int mp, int R);
+const void* kernel_bin64(int kind, int mp);
+const void* kernel_dary32(int d, int mp);
+const void* kernel_dary64(int d, int mp);
+const void* kernel_sumabs();
+const void* kernel_wide();
+constexpr size_t WIDE_LDS_MAX = 64 * 1024;   // bytes of state per wave
+const void* kernel_fill();
+
+// padded column count used for a problem with m columns
+inline int pad_bin32(int m) { return (m + 1) & ~1; }
+inline int pad_bin64(int m) { return (m + 7) & ~7; }
+inline int pad_dary(int m) { return (m + 3) & ~3; }
+
+}  // namespace ld

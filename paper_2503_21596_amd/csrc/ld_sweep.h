@@ -1,0 +1,524 @@
+// Register-resident Gray-code sweeps for gfx950 (CDNA4, wave64).
+//
+// One lane owns one sub-cube of the assignment space: a fixed prefix on the high
+// rows, a Gray-code walk over the mid rows (arXiv:2503.21596 Sec. 2.1.2 for the
+// binary code, Sec. 2.3.2 for the d-ary one) and, for the binary kinds, every
+// pattern of the R low rows scored against the same state.  Because every lane of
+// the grid walks the same mid-row code from the same start, the changed row and
+// its direction are wave-uniform at each step (the group property the paper proves
+// in its Appendix on group-uniform changes), so the row index lives in SGPRs and the
+// row itself is read with scalar loads.
+//
+// Column sums of the int32 path are kept offset-binary (true value + 2^31, as
+// uint32).  With B = sum |M_xy| < 2^31 every partial sum lies in (-2^31, 2^31), so
+// the wrapped additions are exact and a term |s + o| of a score is one
+// v_sad_u32 (|a - b| + c on unsigned operands) against a precomputed operand.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ld_gray.h"
+#include "ld_types.h"
+
+namespace ld {
+
+// Pointer into the constant address space: uniform loads through it become
+// scalar (SMEM) loads.  The tables are read-only for the lifetime of a launch.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const void* p)
+{
+    return (cptr<T>)(uintptr_t)p;
+}
+
+__device__ __forceinline__ uint32_t sad_u32(uint32_t a, uint32_t b, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(acc));
+    return r;
+}
+
+// A value the compiler must keep in a VGPR: the low-row operands are the same
+// in every lane, but read from SGPRs they would not fit (and would spill through
+// v_writelane / v_readlane), so they are copied once into VGPRs.
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x)
+{
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// binary kinds, int32 (offset-binary) path
+
+template <int MP, int KIND, int R>
+struct Bin32 {
+    static constexpr int NW = 1 << R;
+    static constexpr int K = (KIND == KIND_L2) ? 2 : 1;
+    // one stored row of deltas, padded to a multiple of 16 dwords so the whole
+    // row is fetched with s_load_dwordx16
+    static constexpr int RS = (MP + 15) & ~15;
+
+    // best starts at the smallest score of its kind (0, or INT32_MIN for L_marg)
+    __device__ static constexpr uint32_t best_init() { return KIND == KIND_MARG ? 0x80000000u : 0u; }
+
+    __device__ static __forceinline__ void load_offs(const Desc& D, uint32_t (&off)[K][NW][MP])
+    {
+        cptr<uint32_t> o = as_const<uint32_t>(D.offs);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int y = 0; y < MP; ++y) off[k][w][y] = in_vgpr(o[(k * NW + w) * MP + y]);
+    }
+
+    __device__ static __forceinline__ void score(const uint32_t (&s)[MP], const uint32_t (&off)[K][NW][MP],
+                                                 uint32_t& best)
+    {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if constexpr (KIND == KIND_L1) {
+                uint32_t acc = 0;
+#pragma unroll
+                for (int y = 0; y < MP; ++y) acc = sad_u32(s[y], off[0][w][y], acc);
+                best = max(best, acc);
+            } else if constexpr (KIND == KIND_MARG) {
+                uint32_t acc = s[0] - off[0][w][0];   // the linear column, signed
+#pragma unroll
+                for (int y = 1; y < MP; ++y) acc = sad_u32(s[y], off[0][w][y], acc);
+                best = (uint32_t)max((int32_t)best, (int32_t)acc);
+            } else {
+                uint32_t acc = 0;
+#pragma unroll
+                for (int y = 0; y < MP; ++y) {
+                    acc = sad_u32(s[y], off[0][w][y], acc);
+                    acc = sad_u32(s[y], off[1][w][y], acc);
+                }
+                best = max(best, acc);
+            }
+        }
+    }
+
+    // Sweep one prefix value v: start state, then the Gray walk over 2^C words of
+    // the mid rows, scoring NW low patterns at each word.
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, const uint32_t (&off)[K][NW][MP],
+                                                  uint32_t& best)
+    {
+        cptr<uint32_t> base = as_const<uint32_t>(D.base);
+        cptr<int32_t> hid = as_const<int32_t>(D.hid);
+        uint32_t s[MP];
+#pragma unroll
+        for (int y = 0; y < MP; ++y) s[y] = base[y];
+        for (int h = 0; h < D.P; ++h) {
+            const uint32_t mask = 0u - (uint32_t)((v >> h) & 1u);
+#pragma unroll
+            for (int y = 0; y < MP; ++y) s[y] += mask & (uint32_t)hid[h * RS + y];
+        }
+        // The row for the next word is fetched (scalar loads) in the same block
+        // as the scoring of the current word, so its latency hides behind the
+        // v_sad chain.  After the last word the update is dead but harmless.
+        const uint32_t nsteps = 1u << D.C;
+        for (uint32_t t = 0; t < nsteps; ++t) {
+            const uint32_t tn = (t + 1 < nsteps) ? t + 1 : 1;   // always a valid step
+            const uint32_t k = brgc_changed(tn);
+            const uint32_t g = brgc_digit(k, tn);                // new value of digit k
+            const uint64_t addr = __builtin_amdgcn_readfirstlane(
+                                      (uint32_t)((2 * k + (1 - g)) * (RS * 4)))
+                                  + (uint64_t)(uintptr_t)D.mid;
+            cptr<int32_t> row = (cptr<int32_t>)__builtin_assume_aligned((const int32_t*)addr, 64);
+            int32_t nx[RS];
+#pragma unroll
+            for (int y = 0; y < RS; ++y) nx[y] = row[y];
+            score(s, off, best);
+#pragma unroll
+            for (int y = 0; y < MP; ++y) s[y] += (uint32_t)nx[y];
+        }
+    }
+
+    __device__ static __forceinline__ int64_t finish(uint32_t best)
+    {
+        if constexpr (KIND == KIND_MARG) return (int64_t)(int32_t)best;
+        else return (int64_t)best;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// binary kinds, int64 path (sum |M_xy| >= 2^31); no low-row patterns
+
+template <int MP, int KIND>
+struct Bin64 {
+    __device__ static constexpr int64_t best_init() { return INT64_MIN; }
+
+    __device__ static __forceinline__ int64_t score(const int64_t (&s)[MP], cptr<int64_t> cc)
+    {
+        int64_t acc;
+        if constexpr (KIND == KIND_L1) {
+            acc = 0;
+#pragma unroll
+            for (int y = 0; y < MP; ++y) acc += s[y] < 0 ? -s[y] : s[y];
+        } else if constexpr (KIND == KIND_MARG) {
+            acc = s[0];
+#pragma unroll
+            for (int y = 1; y < MP; ++y) acc += s[y] < 0 ? -s[y] : s[y];
+        } else {
+            acc = 0;
+#pragma unroll
+            for (int y = 0; y < MP; ++y) {
+                const int64_t u = s[y], w = cc[y] - s[y];
+                acc += (u < 0 ? -u : u) + (w < 0 ? -w : w);
+            }
+        }
+        return acc;
+    }
+
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, int64_t& best)
+    {
+        cptr<int64_t> base = as_const<int64_t>(D.base);
+        cptr<int64_t> hid = as_const<int64_t>(D.hid);
+        cptr<int64_t> mid = as_const<int64_t>(D.mid);
+        cptr<int64_t> cc = as_const<int64_t>(D.offs);   // column totals (L2)
+        int64_t s[MP];
+#pragma unroll
+        for (int y = 0; y < MP; ++y) s[y] = base[y];
+        for (int h = 0; h < D.P; ++h) {
+            if ((v >> h) & 1u) {
+#pragma unroll
+                for (int y = 0; y < MP; ++y) s[y] += hid[h * MP + y];
+            }
+        }
+        const uint64_t nsteps = 1ull << D.C;
+        for (uint64_t t = 0;;) {
+            const int64_t sc = score(s, cc);
+            best = sc > best ? sc : best;
+            if (++t == nsteps) break;
+            const uint32_t k = brgc_changed(t);
+            const uint32_t g = brgc_digit(k, t);
+            cptr<int64_t> row = mid + (2 * k + (1 - g)) * MP;
+#pragma unroll
+            for (int y = 0; y < MP; ++y) s[y] += row[y];
+        }
+    }
+
+    __device__ static __forceinline__ int64_t finish(int64_t best) { return best; }
+};
+
+// ---------------------------------------------------------------------------
+// d-ary kind (d >= 3): one column-sum vector per message, updated by the two-slot
+// rule of Eq. (update2); only the two touched message norms are recomputed.
+
+template <int MP, int DD>
+struct Dary32 {
+    __device__ static __forceinline__ uint32_t norm(const uint32_t (&g)[MP], uint32_t bias)
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int y = 0; y < MP; ++y) acc = sad_u32(g[y], bias, acc);
+        return acc;
+    }
+
+    __device__ static __forceinline__ void add_row(uint32_t (&g)[MP], uint32_t mask, cptr<int32_t> row)
+    {
+#pragma unroll
+        for (int y = 0; y < MP; ++y) g[y] += mask & (uint32_t)row[y];
+    }
+
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, uint32_t& best)
+    {
+        cptr<uint32_t> base = as_const<uint32_t>(D.base);
+        cptr<int32_t> hid = as_const<int32_t>(D.hid);
+        cptr<int32_t> mid = as_const<int32_t>(D.mid);
+        const uint32_t bias = in_vgpr(0x80000000u);   // one register, not a constant per use
+        uint32_t g[DD][MP];
+#pragma unroll
+        for (int y = 0; y < MP; ++y) g[0][y] = base[y];
+#pragma unroll
+        for (int k = 1; k < DD; ++k)
+#pragma unroll
+            for (int y = 0; y < MP; ++y) g[k][y] = bias;
+
+        uint64_t code = 0, fr = v;
+        if (D.P_tab > 0) {
+            const uint64_t t = v / D.dpow_free;
+            fr = v - t * D.dpow_free;
+            code = D.tab[t];
+        }
+        const int nh = D.P_tab + D.P;
+        for (int h = 0; h < nh; ++h) {
+            uint32_t digit;
+            if (h < D.P_tab) {
+                digit = (uint32_t)(code >> (4 * h)) & 15u;
+            } else {
+                digit = (uint32_t)(fr % DD);
+                fr /= DD;
+            }
+            cptr<int32_t> row = hid + h * MP;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) add_row(g[k], digit == (uint32_t)k ? 0xffffffffu : 0u, row);
+        }
+        uint32_t N[DD];
+#pragma unroll
+        for (int k = 0; k < DD; ++k) N[k] = norm(g[k], bias);
+        uint32_t total = 0;
+#pragma unroll
+        for (int k = 0; k < DD; ++k) total += N[k];
+        best = max(best, total);
+
+        uint32_t nsteps = 1;
+        for (int c = 0; c < D.C; ++c) nsteps *= DD;
+        for (uint32_t t = 1; t < nsteps; ++t) {
+            uint32_t from, to;
+            const uint32_t i = dgc_change<DD>(t, &from, &to);
+            cptr<int32_t> row = mid + i * MP;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) {
+                if ((uint32_t)k == from) {
+#pragma unroll
+                    for (int y = 0; y < MP; ++y) g[k][y] -= (uint32_t)row[y];
+                    N[k] = norm(g[k], bias);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < DD; ++k) {
+                if ((uint32_t)k == to) {
+#pragma unroll
+                    for (int y = 0; y < MP; ++y) g[k][y] += (uint32_t)row[y];
+                    N[k] = norm(g[k], bias);
+                }
+            }
+            total = 0;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) total += N[k];
+            best = max(best, total);
+        }
+    }
+};
+
+template <int MP, int DD>
+struct Dary64 {
+    __device__ static __forceinline__ int64_t norm(const int64_t (&g)[MP])
+    {
+        int64_t acc = 0;
+#pragma unroll
+        for (int y = 0; y < MP; ++y) acc += g[y] < 0 ? -g[y] : g[y];
+        return acc;
+    }
+
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, int64_t& best)
+    {
+        cptr<int64_t> base = as_const<int64_t>(D.base);
+        cptr<int64_t> hid = as_const<int64_t>(D.hid);
+        cptr<int64_t> mid = as_const<int64_t>(D.mid);
+        int64_t g[DD][MP];
+#pragma unroll
+        for (int y = 0; y < MP; ++y) g[0][y] = base[y];
+#pragma unroll
+        for (int k = 1; k < DD; ++k)
+#pragma unroll
+            for (int y = 0; y < MP; ++y) g[k][y] = 0;
+        uint64_t code = 0, fr = v;
+        if (D.P_tab > 0) {
+            const uint64_t t = v / D.dpow_free;
+            fr = v - t * D.dpow_free;
+            code = D.tab[t];
+        }
+        const int nh = D.P_tab + D.P;
+        for (int h = 0; h < nh; ++h) {
+            uint32_t digit;
+            if (h < D.P_tab) {
+                digit = (uint32_t)(code >> (4 * h)) & 15u;
+            } else {
+                digit = (uint32_t)(fr % DD);
+                fr /= DD;
+            }
+            cptr<int64_t> row = hid + h * MP;
+#pragma unroll
+            for (int k = 0; k < DD; ++k)
+                if (digit == (uint32_t)k)
+#pragma unroll
+                    for (int y = 0; y < MP; ++y) g[k][y] += row[y];
+        }
+        int64_t N[DD];
+#pragma unroll
+        for (int k = 0; k < DD; ++k) N[k] = norm(g[k]);
+        int64_t total = 0;
+#pragma unroll
+        for (int k = 0; k < DD; ++k) total += N[k];
+        best = total > best ? total : best;
+        uint32_t nsteps = 1;
+        for (int c = 0; c < D.C; ++c) nsteps *= DD;
+        for (uint32_t t = 1; t < nsteps; ++t) {
+            uint32_t from, to;
+            const uint32_t i = dgc_change<DD>(t, &from, &to);
+            cptr<int64_t> row = mid + i * MP;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) {
+                if ((uint32_t)k == from) {
+#pragma unroll
+                    for (int y = 0; y < MP; ++y) g[k][y] -= row[y];
+                    N[k] = norm(g[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < DD; ++k) {
+                if ((uint32_t)k == to) {
+#pragma unroll
+                    for (int y = 0; y < MP; ++y) g[k][y] += row[y];
+                    N[k] = norm(g[k]);
+                }
+            }
+            total = 0;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) total += N[k];
+            best = total > best ? total : best;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// wave-level max and the per-problem result
+
+__device__ __forceinline__ int64_t wave_max(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void publish(int64_t* result, int64_t v)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0)
+        __hip_atomic_fetch_max(result, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace ld
+
+namespace ld {
+
+// ---------------------------------------------------------------------------
+// Wide sweep: any column count and alphabet.  One wave owns one prefix at a
+// time; lane l holds columns l, l + 64, ... of every state vector in LDS (the
+// entries are private to their lane, so no barrier is needed) and the score of a
+// word is a wave-wide sum.  int64 throughout.  Tables use the int64 layouts with
+// the row stride equal to the real column count.
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t iabs64(int64_t v) { return v < 0 ? -v : v; }
+
+struct Wide {
+    // binary kinds: one state vector s
+    __device__ static int64_t score_bin(const Desc& D, const int64_t* s, const int64_t* tot)
+    {
+        const int lane = threadIdx.x & 63;
+        int64_t acc = 0;
+        for (int y = lane; y < D.m; y += 64) {
+            if (D.kind == KIND_L1) acc += iabs64(s[y]);
+            else if (D.kind == KIND_MARG) acc += (y == 0) ? s[0] : iabs64(s[y]);
+            else acc += iabs64(s[y]) + iabs64(tot[y] - s[y]);
+        }
+        return wave_sum(acc);
+    }
+
+    __device__ static int64_t norm(const Desc& D, const int64_t* g)
+    {
+        const int lane = threadIdx.x & 63;
+        int64_t acc = 0;
+        for (int y = lane; y < D.m; y += 64) acc += iabs64(g[y]);
+        return wave_sum(acc);
+    }
+
+    __device__ static void prefix_bin(const Desc& D, uint64_t v, int64_t* s, int64_t& best)
+    {
+        const int lane = threadIdx.x & 63, m = D.m;
+        const int64_t* base = (const int64_t*)D.base;
+        const int64_t* hid = (const int64_t*)D.hid;
+        const int64_t* mid = (const int64_t*)D.mid;
+        const int64_t* tot = (const int64_t*)D.offs;
+        for (int y = lane; y < m; y += 64) {
+            int64_t a = base[y];
+            for (int h = 0; h < D.P; ++h)
+                if ((v >> h) & 1u) a += hid[(size_t)h * m + y];
+            s[y] = a;
+        }
+        int64_t sc = score_bin(D, s, tot);
+        best = sc > best ? sc : best;
+        const uint64_t nsteps = 1ull << D.C;
+        for (uint64_t t = 1; t < nsteps; ++t) {
+            const uint32_t k = brgc_changed(t);
+            const uint32_t g = brgc_digit(k, t);
+            const int64_t* row = mid + (size_t)(2 * k + (1 - g)) * m;
+            for (int y = lane; y < m; y += 64) s[y] += row[y];
+            sc = score_bin(D, s, tot);
+            best = sc > best ? sc : best;
+        }
+    }
+
+    // d-ary: D.d state vectors g_k = LDS[k*m ...]
+    __device__ static void prefix_dary(const Desc& D, uint64_t v, int64_t* g, int64_t* N, int64_t& best)
+    {
+        const int lane = threadIdx.x & 63, m = D.m, K = D.d;
+        const int64_t* base = (const int64_t*)D.base;
+        const int64_t* hid = (const int64_t*)D.hid;
+        const int64_t* mid = (const int64_t*)D.mid;
+        for (int y = lane; y < m; y += 64) {
+            g[y] = base[y];
+            for (int k = 1; k < K; ++k) g[(size_t)k * m + y] = 0;
+        }
+        uint64_t code = 0, fr = v;
+        if (D.P_tab > 0) {
+            const uint64_t t = v / D.dpow_free;
+            fr = v - t * D.dpow_free;
+            code = D.tab[t];
+        }
+        const int nh = D.P_tab + D.P;
+        for (int h = 0; h < nh; ++h) {
+            uint32_t digit;
+            if (h < D.P_tab) {
+                digit = (uint32_t)(code >> (4 * h)) & 15u;
+            } else {
+                digit = (uint32_t)(fr % (uint64_t)K);
+                fr /= (uint64_t)K;
+            }
+            const int64_t* row = hid + (size_t)h * m;
+            for (int y = lane; y < m; y += 64) g[(size_t)digit * m + y] += row[y];
+        }
+        int64_t total = 0;
+        for (int k = 0; k < K; ++k) {
+            N[k] = norm(D, g + (size_t)k * m);
+            total += N[k];
+        }
+        best = total > best ? total : best;
+        uint64_t nsteps = 1;
+        for (int c = 0; c < D.C; ++c) nsteps *= (uint64_t)K;
+        for (uint64_t t = 1; t < nsteps; ++t) {
+            uint32_t from, to;
+            const uint32_t i = dgc_change_rt((uint32_t)K, t, &from, &to);
+            const int64_t* row = mid + (size_t)i * m;
+            int64_t* gf = g + (size_t)from * m;
+            int64_t* gt = g + (size_t)to * m;
+            for (int y = lane; y < m; y += 64) {
+                gf[y] -= row[y];
+                gt[y] += row[y];
+            }
+            const int64_t nf = norm(D, gf), nt = norm(D, gt);
+            total += (nf - N[from]) + (nt - N[to]);
+            N[from] = nf;
+            N[to] = nt;
+            best = total > best ? total : best;
+        }
+    }
+};
+
+}  // namespace ld

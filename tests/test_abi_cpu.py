@@ -1,0 +1,152 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports every
+symbol include/ld.h declares, validates arguments before touching the device, and
+its planner and Gray-code helpers match what the paper fixes."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+L = pytest.importorskip("paper_2503_21596_amd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ld.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ld_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert "ld_norm" in names and "ld_norm_batch" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in L.SIGNATURES, name
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 2, 2, 1, 0), 1),
+    (("M", 0, 2, 1, 0), 1),
+    (("M", 2, 0, 1, 0), 1),
+    (("M", 2, 2, 0, 0), 1),
+    (("M", 2, 2, 1, 2), 1),
+    (("M", 2, 2, 2, 1), 2),     # marginals are defined only for the local bound
+])
+def test_validation_before_device(lib, args, code):
+    M = np.ones((2, 2), dtype=np.int32)
+    ptr = None if args[0] is None else M.ctypes.data
+    v = lib.ld_norm(ptr, *args[1:])
+    assert v == L.INT64_MIN
+    assert lib.ld_last_error() == code
+    assert lib.ld_error_string(code)
+
+
+def test_range_validation(lib):
+    M = np.ones((4, 3), dtype=np.int32)
+    assert lib.ld_norm_range(M.ctypes.data, 4, 3, 1, 0, 2, 3, 3) == L.INT64_MIN   # empty range
+    assert lib.ld_last_error() == L.LD_EINVAL
+    assert lib.ld_norm_range(M.ctypes.data, 4, 3, 1, 0, 2, 0, 5) == L.INT64_MIN   # past 2^q
+    assert lib.ld_norm_range(M.ctypes.data, 4, 3, 1, 0, 4, 0, 1) == L.INT64_MIN   # q > n - 1
+
+
+def test_plan_transpose_and_zero_removal():
+    M = np.zeros((9, 5), dtype=np.int32)
+    M[1:8, 0:4] = synth.matrix(0, 7, 4, -5, 5, "abi")
+    M[1:8, 0:4][M[1:8, 0:4] == 0] = 1
+    p = L.plan(M, 1, 0)
+    assert p["status"] == 0 and p["kind_name"] == "L1"
+    assert (p["n"], p["m"], p["transposed"]) == (4, 7, 1)     # 7x4 after dropping zeros, transposed
+    p2 = L.plan(M, 2, 0)
+    assert (p2["n"], p2["m"], p2["transposed"]) == (7, 4, 0)  # no transposition for d >= 2
+
+
+def test_plan_marginal_rules():
+    M = synth.matrix(1, 5, 5, -5, 5, "abi")
+    Z = M.copy()
+    Z[0, :] = 0
+    Z[:, 0] = 0
+    p = L.plan(Z, 1, 1)
+    assert p["kind_name"] == "L1" and (p["n"], p["m"]) == (4, 4)   # Sec. 2.2: no marginals left
+    p = L.plan(M, 1, 1)
+    assert p["kind_name"] == "L_marg"
+
+
+def test_plan_int64_boundary():
+    # int32 path iff sum |M_xy| <= 2^31 - 1
+    M = np.array([[2**30, 2**30 - 1], [0, 0]], dtype=np.int64)
+    M = M[:1].astype(np.int32)
+    assert L.plan(M, 1, 0)["i64"] == 0
+    M2 = np.array([[2**30, 2**30]], dtype=np.int32)
+    assert L.plan(M2, 1, 0)["i64"] == 1
+
+
+def test_plan_dary_counts():
+    # restricted-growth prefixes: 16 rows, d = 3 -> 1094 strings of length 8 times 3^8
+    p = L.plan(synth.config_pm(0), 3, 0)
+    assert p["kind_name"] == "L_d" and p["P_tab"] == 8
+    assert p["words"] == 1094 * 3 ** 8
+    p = L.plan(synth.config_pm(0), 4, 0)
+    assert p["words"] == 2795 * 4 ** 8
+    # d >= rows: the value is sum |M|, no search
+    assert L.plan(synth.matrix(0, 3, 4, -3, 3, "abi"), 3, 0)["kind_name"] in ("sum|M|",)
+
+
+def test_plan_headline_shape():
+    p = L.plan(synth.config_42_l1(0), 1, 0)
+    assert p["words"] == 2.0 ** 41
+    assert p["R"] + p["C"] + p["P"] == 41
+
+
+def test_plan_wide_and_too_big():
+    # more than 64 columns: the wide (LDS-state) kernel takes it
+    M = synth.matrix(2, 3, 70, 1, 9, "abi")
+    p = L.plan(M, 1, 0)
+    assert p["status"] == 0 and p["words"] == 4
+    # 64 rows and 64 columns: 2^63 sign vectors even after the sign symmetry (Sec. 2.1.3)
+    B = synth.matrix(3, 64, 64, 1, 9, "abi")
+    assert L.plan(B, 1, 0)["status"] == L.LD_ETOOBIG
+
+
+def test_brgc_table1(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "brgc_table1.json")))
+    for i, row in g["rows_by_digit"].items():
+        assert [L.gray_digit(2, int(i), j) for j in range(16)] == row
+    for j, tag in enumerate(g["change_row"]):
+        if j == 0:
+            continue  # word 0 differs from word 15 (cyclic); the helper starts at j >= 1
+        i, f, t = L.gray_change(2, j)
+        assert tag == f"{i}{'+' if t == 1 else '-'}" and f == 1 - t
+
+
+def test_trgc_table3(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "trgc_table3.json")))
+    for i, row in g["rows_by_digit"].items():
+        assert [L.gray_digit(3, int(i), j) for j in range(27)] == row
+    for j, dig in enumerate(g["change_row"]):
+        if dig is None:
+            continue
+        i, f, t = L.gray_change(3, j)
+        assert i == dig
+        assert f == L.gray_digit(3, i, j - 1) and t == L.gray_digit(3, i, j)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_gray_hamming_one(d):
+    # consecutive words differ in exactly the reported digit
+    for j in range(1, d ** 4):
+        i, f, t = L.gray_change(d, j)
+        prev = [L.gray_digit(d, k, j - 1) for k in range(5)]
+        cur = [L.gray_digit(d, k, j) for k in range(5)]
+        diff = [k for k in range(5) if prev[k] != cur[k]]
+        assert diff == [i] and prev[i] == f and cur[i] == t
