@@ -31,6 +31,28 @@ def alg_ops_per_word(kind: str, m: int) -> int:
     raise ValueError(kind)
 
 
+KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip"]
+TRAFFIC_PROFILE = "profiles/k_bin32_l1_42x42.md"
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3 summary,
+    or None when the kernel sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", " ", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
+    if fields.get("kernel_source_sha256_16") != h[:16] or "traffic_bytes" not in fields:
+        return None
+    return float(fields["traffic_bytes"])
+
+
 def cpu_baseline(M, target_s: float = 12.0):
     """The oracle (as it stands) on a bounded sample of the same problem: the
     sign vectors whose last q = 20 rows take a few fixed prefix values."""
@@ -58,6 +80,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
+                         "known traffic, to scale the HBM counters of a profiler run)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -128,7 +153,7 @@ def main():
         "matches_oracle": (value == golden) if golden is not None else None,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_VALU_PEAK,
-                     "traffic": None,
+                     "traffic": profiled_traffic(),
                      "ops_per_step": ops, "kernel_ms": kavg},
         "wall_s": wall,
     }
@@ -143,6 +168,13 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(M)
     h.close()
+    if a.calib_copy_mib:
+        nbytes = a.calib_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
 
