@@ -60,13 +60,28 @@ typedef struct {
     int32_t n, m, d, marginals;
 } ld_problem;
 
-/* ld_norm_batch -- many independent problems in one persistent launch.
+/* ld_norm_batch -- many independent problems, same values as ld_norm each.
+ * The problems are planned on host threads, packed into one device image and
+ * swept by persistent work-queue launches (one per kernel shape) whose waves pull
+ * (problem, prefix range) items, longest first, until the queue is empty.
  * out[i] receives problem i's value, or INT64_MIN on error; status (nullable)
  * receives each problem's error code.  hip_stream: a hipStream_t, or NULL for
  * the library's own stream; with a caller stream the call still returns after
  * the results are in out[].  Returns LD_OK, or the first error code met. */
 int ld_norm_batch(const ld_problem* probs, int32_t count, int64_t* out, int32_t* status,
                   void* hip_stream);
+
+/* Reusable batch: ld_batch_prepare plans and uploads the problems once (the
+ * matrices are not retained) and captures the reset, the queue launches and the
+ * result copy in a HIP graph; ld_batch_run replays it on hip_stream (NULL: the
+ * handle's stream), waits, and writes count values to out (INT64_MIN and an
+ * error return for problems that failed to plan).  ld_batch_last_ms: device time
+ * of the last run (HIP events around the graph).  One thread at a time per handle. */
+typedef struct ld_batch ld_batch;
+ld_batch* ld_batch_prepare(const ld_problem* probs, int32_t count, int32_t* status);
+int ld_batch_run(ld_batch* b, void* hip_stream, int64_t* out);
+float ld_batch_last_ms(ld_batch* b);
+void ld_batch_release(ld_batch* b);
 
 /* ld_norm_range -- the maximum over part of the search space, for spot checks
  * at full size.  No preprocessing.  Row 0 is fixed (a_0 = +1 for d = 1, message
@@ -132,6 +147,16 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
  * r_drop: 1 to score one low row fewer per state than the register budget allows;
  * dary_ptab: rows covered by restricted-growth prefixes (<= 16). */
 void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab);
+
+/* Autotuner.  The paper found no general rule for the launch shape and advises
+ * timing a smaller matrix first (Sec. 4).  ld_autotune times candidate shapes on
+ * the current device -- words per prefix and per queue item for batches, lane
+ * count and low rows for plain calls -- within about budget_seconds, applies the
+ * fastest, and writes them as JSON to path (NULL: do not write).
+ * ld_load_tuning applies a file written by ld_autotune.  Shapes change speed only,
+ * never values. */
+int ld_autotune(const char* path, double budget_seconds);
+int ld_load_tuning(const char* path);
 
 #ifdef __cplusplus
 }

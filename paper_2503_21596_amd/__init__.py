@@ -72,6 +72,12 @@ SIGNATURES = {
     "ld_last_kernel_ms": (ctypes.c_float, [_P]),
     "ld_prepared_plan": (ctypes.c_int, [_P, _P]),
     "ld_release": (None, [_P]),
+    "ld_batch_prepare": (_P, [_P, _I32, _P]),
+    "ld_batch_run": (ctypes.c_int, [_P, _P, _P]),
+    "ld_batch_last_ms": (ctypes.c_float, [_P]),
+    "ld_batch_release": (None, [_P]),
+    "ld_autotune": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double]),
+    "ld_load_tuning": (ctypes.c_int, [ctypes.c_char_p]),
 }
 
 _lib = None
@@ -83,6 +89,13 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_21596_amd._build.build()")
+        # torch ships its own libamdhip64.so.7; loading it first makes libld.so bind to
+        # that same HIP runtime, so streams and events pass between the two and torch
+        # still sees the GPU (two runtimes in one process do not share devices)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)   # a missing export is a broken build: raise
@@ -186,6 +199,42 @@ class Prepared:
             pass
 
 
+class Batch:
+    """A reusable batch (ld_batch_prepare): tables resident, launches in a HIP graph."""
+
+    def __init__(self, problems: Sequence[Tuple]):
+        mats = [_mat(p[0]) for p in problems]
+        arr = (ld_problem * max(1, len(problems)))()
+        for i, (a, p) in enumerate(zip(mats, problems)):
+            arr[i] = ld_problem(a.ctypes.data, a.shape[0], a.shape[1], int(p[1]), int(p[2]))
+        self.count = len(problems)
+        self.status = np.zeros(self.count, dtype=np.int32)
+        self._h = lib().ld_batch_prepare(ctypes.addressof(arr), self.count, self.status.ctypes.data)
+        if not self._h:
+            raise _err()
+
+    def run(self, stream=None, check: bool = True) -> np.ndarray:
+        out = np.zeros(self.count, dtype=np.int64)
+        rc = lib().ld_batch_run(self._h, _stream_handle(stream), out.ctypes.data)
+        if rc != LD_OK and check:
+            raise _err(rc)
+        return out
+
+    def last_ms(self) -> float:
+        return float(lib().ld_batch_last_ms(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ld_batch_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def plan(M, d: int = 1, marginals: int = 0) -> dict:
     a = _mat(M)
     info = ld_plan_info()
@@ -210,12 +259,16 @@ def set_sweep_shape(p_target: int = 0, c_min: int = 0, r_drop: int = -1, dary_pt
     lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab)
 
 
-def autotune(path: str, budget_seconds: float = 20.0) -> int:
-    return int(lib().ld_autotune(path.encode(), budget_seconds))
+def autotune(path: Optional[str] = None, budget_seconds: float = 20.0) -> None:
+    rc = lib().ld_autotune(path.encode() if path else None, float(budget_seconds))
+    if rc != LD_OK:
+        raise _err(rc)
 
 
-def load_tuning(path: str) -> int:
-    return int(lib().ld_load_tuning(path.encode()))
+def load_tuning(path: str) -> None:
+    rc = lib().ld_load_tuning(path.encode())
+    if rc != LD_OK:
+        raise _err(rc)
 
 
 class Server:

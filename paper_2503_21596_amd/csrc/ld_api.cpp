@@ -1,15 +1,15 @@
-// C ABI: plain, range and introspection entry points (see include/ld.h).
+// C ABI: plain, range, prepared and introspection entry points (see include/ld.h).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
-#include <mutex>
 #include <vector>
 
 #include "ld.h"
 #include "ld_api_internal.h"
 #include "ld_gray.h"
 #include "ld_plan.h"
+#include "ld_program.h"
 #include "ld_registry.h"
 
 namespace ld {
@@ -18,8 +18,19 @@ thread_local int t_last_error = LD_OK;
 
 void set_error(int code) { t_last_error = code; }
 
+bool device_ok(int* dev_out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return false;
+    if (dev_out) *dev_out = dev;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
-// per-thread device context: stream, device blob buffer, pinned staging, result
+// per-thread device context: stream, device image buffer, pinned staging, results
 
 namespace {
 
@@ -30,14 +41,13 @@ struct Ctx {
     size_t dcap = 0;
     void* hbuf = nullptr;
     size_t hcap = 0;
-    int64_t* dres = nullptr;
     int64_t* hres = nullptr;
+    size_t rcap = 0;
     ~Ctx()
     {
-        // buffers are released at thread exit; errors here cannot be reported
+        // released at thread exit; errors here cannot be reported
         if (dbuf) (void)hipFree(dbuf);
         if (hbuf) (void)hipHostFree(hbuf);
-        if (dres) (void)hipFree(dres);
         if (hres) (void)hipHostFree(hres);
         if (stream) (void)hipStreamDestroy(stream);
     }
@@ -48,68 +58,60 @@ thread_local Ctx t_ctx;
 bool ctx_ready(Ctx& c)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
-    if (c.device == dev && c.stream) return true;
-    if (c.stream) return false;   // device switched mid-thread: not supported
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return false;
+    if (c.stream) return hipGetDevice(&dev) == hipSuccess && dev == c.device;
+    if (!device_ok(&dev)) return false;
     if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return false;
-    if (hipMalloc((void**)&c.dres, 64) != hipSuccess) return false;
-    if (hipHostMalloc((void**)&c.hres, 64, hipHostMallocDefault) != hipSuccess) return false;
     c.device = dev;
     return true;
 }
 
-bool ensure(Ctx& c, size_t bytes)
+bool ensure(Ctx& c, size_t bytes, size_t nres)
 {
-    if (bytes <= c.dcap) return true;
-    size_t cap = std::max<size_t>(bytes, 1 << 20);
-    if (c.dbuf) (void)hipFree(c.dbuf);
-    if (c.hbuf) (void)hipHostFree(c.hbuf);
-    c.dbuf = c.hbuf = nullptr;
-    c.dcap = c.hcap = 0;
-    if (hipMalloc(&c.dbuf, cap) != hipSuccess) return false;
-    if (hipHostMalloc(&c.hbuf, cap, hipHostMallocDefault) != hipSuccess) return false;
-    c.dcap = c.hcap = cap;
+    if (bytes > c.dcap) {
+        const size_t cap = std::max<size_t>(bytes, (size_t)1 << 20);
+        if (c.dbuf) (void)hipFree(c.dbuf);
+        if (c.hbuf) (void)hipHostFree(c.hbuf);
+        c.dbuf = c.hbuf = nullptr;
+        c.dcap = c.hcap = 0;
+        if (hipMalloc(&c.dbuf, cap) != hipSuccess) return false;
+        if (hipHostMalloc(&c.hbuf, cap, hipHostMallocDefault) != hipSuccess) return false;
+        c.dcap = c.hcap = cap;
+    }
+    if (nres > c.rcap) {
+        const size_t cap = std::max<size_t>(nres, 1024);
+        if (c.hres) (void)hipHostFree(c.hres);
+        c.hres = nullptr;
+        c.rcap = 0;
+        if (hipHostMalloc((void**)&c.hres, 8 * cap, hipHostMallocDefault) != hipSuccess) return false;
+        c.rcap = cap;
+    }
     return true;
 }
 
 }  // namespace
 
-uint32_t grid_blocks(uint64_t n_prefix)
+// Solve a set of planned problems synchronously on the calling thread's buffers.
+// out[i] receives problem i's value; problems with value 0 need no search.
+bool run_plans_sync(const std::vector<const Plan*>& plans, const ItemShape& shape, int64_t* out, hipStream_t s)
 {
-    const uint64_t lanes = std::max<uint64_t>(n_prefix, 1);
-    const uint64_t blocks = (lanes + 255) / 256;
-    return (uint32_t)std::min<uint64_t>(blocks, 1u << 16);
-}
-
-bool launch_sweep(const Plan& p, const void* dev_blob, int64_t* dres, hipStream_t s)
-{
-    Desc D = make_desc(p, dev_blob, dres);
-    void* args[] = {(void*)&D};
-    if (p.wide) {
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(p.n_prefix, 1), 1u << 16);
-        return hipLaunchKernel(p.kernel, dim3(blocks), dim3(64), args, p.lds, s) == hipSuccess;
+    Ctx& c = t_ctx;
+    Program P = build_program(plans, shape);
+    if (!ctx_ready(c) || !ensure(c, P.image.size(), P.n_probs)) return false;
+    if (!s) s = c.stream;
+    patch_program(P, c.dbuf);
+    std::memcpy(c.hbuf, P.image.data(), P.image.size());
+    bool ok = hipMemcpyAsync(c.dbuf, c.hbuf, P.image.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && enqueue_program(P, s, c.hres);
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return false;
     }
-    return hipLaunchKernel(p.kernel, dim3(grid_blocks(p.n_prefix)), dim3(256), args, 0, s) == hipSuccess;
+    std::memcpy(out, c.hres, 8 * (size_t)P.n_probs);
+    for (int i : P.zero) out[i] = 0;
+    return true;
 }
 
-bool launch_plan(const Plan& p, const void* dev_blob, int64_t* dres, hipStream_t s)
-{
-    if (p.kind == PK_SUMABS) {
-        const int32_t* dM = (const int32_t*)dev_blob;
-        int64_t count = (int64_t)p.n * p.m;
-        void* args[] = {(void*)&dM, (void*)&count, (void*)&dres};
-        return hipLaunchKernel(kernel_sumabs(), dim3(1), dim3(256), args, 0, s) == hipSuccess;
-    }
-    int64_t cnt = 1, val = INT64_MIN;
-    void* fargs[] = {(void*)&dres, (void*)&cnt, (void*)&val};
-    if (hipLaunchKernel(kernel_fill(), dim3(1), dim3(256), fargs, 0, s) != hipSuccess) return false;
-    return launch_sweep(p, dev_blob, dres, s);
-}
-
-// Run one planned problem synchronously on the calling thread's stream.
 int64_t run_plan_sync(const Plan& p)
 {
     if (p.status != LD_OK) {
@@ -117,22 +119,12 @@ int64_t run_plan_sync(const Plan& p)
         return INT64_MIN;
     }
     if (p.kind == PK_ZERO) return 0;
-    Ctx& c = t_ctx;
-    if (!ctx_ready(c) || !ensure(c, p.blob.size())) {
+    int64_t v = INT64_MIN;
+    if (!run_plans_sync({&p}, ItemShape{}, &v, nullptr)) {
         set_error(LD_EHIP);
         return INT64_MIN;
     }
-    std::memcpy(c.hbuf, p.blob.data(), p.blob.size());
-    bool ok = hipMemcpyAsync(c.dbuf, c.hbuf, p.blob.size(), hipMemcpyHostToDevice, c.stream) == hipSuccess;
-    ok = ok && launch_plan(p, c.dbuf, c.dres, c.stream);
-    ok = ok && hipMemcpyAsync(c.hres, c.dres, 8, hipMemcpyDeviceToHost, c.stream) == hipSuccess;
-    ok = ok && hipStreamSynchronize(c.stream) == hipSuccess;
-    if (!ok) {
-        (void)hipGetLastError();
-        set_error(LD_EHIP);
-        return INT64_MIN;
-    }
-    return *c.hres;
+    return v;
 }
 
 }  // namespace ld
@@ -141,10 +133,10 @@ using namespace ld;
 
 struct ld_prepared {
     Plan plan;
+    Program prog;
     int device = -1;
     hipStream_t own = nullptr;
-    void* dblob = nullptr;
-    int64_t* dres = nullptr;
+    void* dev = nullptr;
     int64_t* hres = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float last_ms = 0.f;
@@ -173,8 +165,7 @@ void info_from_plan(const Plan& p, ld_plan_info* info)
 void release(ld_prepared* h)
 {
     if (!h) return;
-    if (h->dblob) (void)hipFree(h->dblob);
-    if (h->dres) (void)hipFree(h->dres);
+    if (h->dev) (void)hipFree(h->dev);
     if (h->hres) (void)hipHostFree(h->hres);
     if (h->e0) (void)hipEventDestroy(h->e0);
     if (h->e1) (void)hipEventDestroy(h->e1);
@@ -186,6 +177,19 @@ void release(ld_prepared* h)
 
 extern "C" {
 
+int64_t ld_norm(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals)
+{
+    Plan p = make_plan(M, n, m, d, marginals, get_shape());
+    return run_plan_sync(p);
+}
+
+int64_t ld_norm_range(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals, int32_t q,
+                      uint64_t prefix_begin, uint64_t prefix_end)
+{
+    Plan p = make_range_plan(M, n, m, d, marginals, q, prefix_begin, prefix_end);
+    return run_plan_sync(p);
+}
+
 ld_prepared* ld_prepare(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals)
 {
     ld_prepared* h = new ld_prepared;
@@ -195,17 +199,15 @@ ld_prepared* ld_prepare(const int32_t* M, int32_t n, int32_t m, int32_t d, int32
         delete h;
         return nullptr;
     }
-    bool ok = hipGetDevice(&h->device) == hipSuccess;
-    hipDeviceProp_t prop;
-    ok = ok && hipGetDeviceProperties(&prop, h->device) == hipSuccess &&
-         std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    h->prog = build_program({&h->plan}, ItemShape{});
+    bool ok = device_ok(&h->device);
     ok = ok && hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreate(&h->e0) == hipSuccess && hipEventCreate(&h->e1) == hipSuccess;
-    ok = ok && hipMalloc((void**)&h->dres, 64) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&h->hres, 64, hipHostMallocDefault) == hipSuccess;
-    if (ok && !h->plan.blob.empty()) {
-        ok = hipMalloc(&h->dblob, h->plan.blob.size()) == hipSuccess &&
-             hipMemcpy(h->dblob, h->plan.blob.data(), h->plan.blob.size(), hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMalloc(&h->dev, h->prog.image.size()) == hipSuccess;
+    if (ok) {
+        patch_program(h->prog, h->dev);
+        ok = hipMemcpy(h->dev, h->prog.image.data(), h->prog.image.size(), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -228,19 +230,11 @@ int ld_run(ld_prepared* h, void* hip_stream, int64_t* value)
         return LD_OK;
     }
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : h->own;
-    bool ok = true;
-    if (h->plan.kind == PK_SUMABS) {
-        ok = hipEventRecord(h->e0, s) == hipSuccess && launch_plan(h->plan, h->dblob, h->dres, s) &&
-             hipEventRecord(h->e1, s) == hipSuccess;
-    } else {
-        int64_t cnt = 1, val = INT64_MIN;
-        void* fargs[] = {(void*)&h->dres, (void*)&cnt, (void*)&val};
-        ok = hipLaunchKernel(kernel_fill(), dim3(1), dim3(256), fargs, 0, s) == hipSuccess;
-        ok = ok && hipEventRecord(h->e0, s) == hipSuccess;
-        ok = ok && launch_sweep(h->plan, h->dblob, h->dres, s);
-        ok = ok && hipEventRecord(h->e1, s) == hipSuccess;
-    }
-    ok = ok && hipMemcpyAsync(h->hres, h->dres, 8, hipMemcpyDeviceToHost, s) == hipSuccess;
+    bool ok = hipEventRecord(h->e0, s) == hipSuccess;
+    ok = ok && enqueue_program(h->prog, s, nullptr);
+    ok = ok && hipEventRecord(h->e1, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(h->hres, (uint8_t*)h->dev + h->prog.off_results, 8, hipMemcpyDeviceToHost, s) ==
+                   hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     ok = ok && hipEventElapsedTime(&h->last_ms, h->e0, h->e1) == hipSuccess;
     if (!ok) {
@@ -262,19 +256,6 @@ int ld_prepared_plan(const ld_prepared* h, ld_plan_info* info)
 }
 
 void ld_release(ld_prepared* h) { release(h); }
-
-int64_t ld_norm(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals)
-{
-    Plan p = make_plan(M, n, m, d, marginals, get_shape());
-    return run_plan_sync(p);
-}
-
-int64_t ld_norm_range(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals, int32_t q,
-                      uint64_t prefix_begin, uint64_t prefix_end)
-{
-    Plan p = make_range_plan(M, n, m, d, marginals, q, prefix_begin, prefix_end);
-    return run_plan_sync(p);
-}
 
 int ld_last_error(void) { return t_last_error; }
 

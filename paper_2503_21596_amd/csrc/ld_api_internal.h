@@ -3,20 +3,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "ld_plan.h"
+#include "ld_program.h"
 
 namespace ld {
 
 void set_error(int code);
 
-// blocks of 256 lanes for n_prefix prefixes (grid-stride beyond 2^16 blocks)
-uint32_t grid_blocks(uint64_t n_prefix);
+// true if the current HIP device is a gfx950; its index in *dev
+bool device_ok(int* dev);
 
-// enqueue the sweep kernel of one planned problem (result slot already reset)
-bool launch_sweep(const Plan& p, const void* dev_blob, int64_t* dres, hipStream_t s);
-
-// enqueue the result reset (where needed) and the sweep of one planned problem
-bool launch_plan(const Plan& p, const void* dev_blob, int64_t* dres, hipStream_t s);
+// Solve planned problems (all with status LD_OK) on the calling thread's
+// buffers; s = nullptr uses the thread's own stream.  Synchronous.
+bool run_plans_sync(const std::vector<const Plan*>& plans, const ItemShape& shape, int64_t* out, hipStream_t s);
 
 int64_t run_plan_sync(const Plan& p);
 

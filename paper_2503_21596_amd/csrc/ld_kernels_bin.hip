@@ -12,41 +12,53 @@
 
 namespace ld {
 
-// One launch covers prefixes [0, n_prefix) of one problem; lane l takes prefixes
-// l, l + T, l + 2T, ... (T = grid size in lanes).  Lanes past the end repeat the
-// last prefix, which cannot change a maximum, so every wave stays converged.
+// Persistent queue kernel: each wave pops items (problem, prefix range); lane l
+// of the wave takes prefixes p0 + l, p0 + l + 64, ... of the item.  Lanes past
+// the item's end repeat its last prefix, which cannot change a maximum, so the
+// wave stays converged.  The low-row operands are reloaded only when the
+// problem changes between consecutive items.
 template <int MP, int KIND, int R>
-__global__ __launch_bounds__(256) void k_bin32(Desc D)
+__global__ __launch_bounds__(256) void k_bin32(QArgs q)
 {
     using B = Bin32<MP, KIND, R>;
+    const uint32_t lane = threadIdx.x & 63;
     uint32_t off[B::K][B::NW][MP];
-    B::load_offs(D, off);
-    uint32_t best = B::best_init();
-    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
-    for (uint64_t j = 0; j < rounds; ++j) {
-        uint64_t p = lane + j * nth;
-        if (p >= D.n_prefix) p = D.n_prefix - 1;
-        B::prefix(D, D.pfx_base + p, off, best);
+    uint32_t loaded = 0xffffffffu;
+    Item it;
+    while (pop_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        if (it.prob != loaded) {
+            B::load_offs(D, off);
+            loaded = it.prob;
+        }
+        uint32_t best = B::best_init();
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            B::prefix(D, D.pfx_base + it.p0 + i, off, best);
+        }
+        publish(D.result, B::finish(best));
     }
-    publish(D.result, B::finish(best));
 }
 
 template <int MP, int KIND>
-__global__ __launch_bounds__(256) void k_bin64(Desc D)
+__global__ __launch_bounds__(256) void k_bin64(QArgs q)
 {
     using B = Bin64<MP, KIND>;
-    int64_t best = B::best_init();
-    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
-    for (uint64_t j = 0; j < rounds; ++j) {
-        uint64_t p = lane + j * nth;
-        if (p >= D.n_prefix) p = D.n_prefix - 1;
-        B::prefix(D, D.pfx_base + p, best);
+    const uint32_t lane = threadIdx.x & 63;
+    Item it;
+    while (pop_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        int64_t best = B::best_init();
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            B::prefix(D, D.pfx_base + it.p0 + i, best);
+        }
+        publish(D.result, B::finish(best));
     }
-    publish(D.result, B::finish(best));
 }
 
 namespace {

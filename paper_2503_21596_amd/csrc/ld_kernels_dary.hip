@@ -3,76 +3,97 @@
 #include <utility>
 
 #include "ld_registry.h"
+#include "ld_program.h"
 #include "ld_sweep.h"
 
 namespace ld {
 
+// Persistent queue kernels (see k_bin32): one item = a range of prefixes of one
+// problem, one lane per prefix.
 template <int MP, int DD>
-__global__ __launch_bounds__(256) void k_dary32(Desc D)
+__global__ __launch_bounds__(256) void k_dary32(QArgs q)
 {
-    uint32_t best = 0;
-    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
-    for (uint64_t j = 0; j < rounds; ++j) {
-        uint64_t p = lane + j * nth;
-        if (p >= D.n_prefix) p = D.n_prefix - 1;
-        Dary32<MP, DD>::prefix(D, D.pfx_base + p, best);
+    const uint32_t lane = threadIdx.x & 63;
+    Item it;
+    while (pop_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        uint32_t best = 0;
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            Dary32<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, best);
+        }
+        publish(D.result, (int64_t)best);
     }
-    publish(D.result, (int64_t)best);
 }
 
 template <int MP, int DD>
-__global__ __launch_bounds__(256) void k_dary64(Desc D)
+__global__ __launch_bounds__(256) void k_dary64(QArgs q)
 {
-    int64_t best = INT64_MIN;
-    const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t rounds = (D.n_prefix + nth - 1) / nth;
-    for (uint64_t j = 0; j < rounds; ++j) {
-        uint64_t p = lane + j * nth;
-        if (p >= D.n_prefix) p = D.n_prefix - 1;
-        Dary64<MP, DD>::prefix(D, D.pfx_base + p, best);
+    const uint32_t lane = threadIdx.x & 63;
+    Item it;
+    while (pop_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        int64_t best = INT64_MIN;
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            Dary64<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, best);
+        }
+        publish(D.result, best);
     }
-    publish(D.result, best);
 }
 
-// Wide sweep (any column count / alphabet), one wave per block; dynamic LDS holds
+// Wide sweep (any column count / alphabet), one wave per block; each item's
+// prefixes are swept one after another by the whole wave.  Dynamic LDS holds
 // the state vectors and, for d-ary problems, the d message norms.
-__global__ __launch_bounds__(64) void k_wide(Desc D)
+__global__ __launch_bounds__(64) void k_wide(QArgs q)
 {
     extern __shared__ int64_t lds[];
-    int64_t best = INT64_MIN;
-    for (uint64_t p = blockIdx.x; p < D.n_prefix; p += gridDim.x) {
-        if (D.kind == KIND_LD) Wide::prefix_dary(D, D.pfx_base + p, lds, lds + (size_t)D.d * D.m, best);
-        else Wide::prefix_bin(D, D.pfx_base + p, lds, best);
+    Item it;
+    while (pop_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        int64_t best = INT64_MIN;
+        for (uint32_t i = 0; i < it.count; ++i) {
+            const uint64_t v = D.pfx_base + it.p0 + i;
+            if (D.kind == KIND_LD) Wide::prefix_dary(D, v, lds, lds + (size_t)D.d * D.m, best);
+            else Wide::prefix_bin(D, v, lds, best);
+        }
+        publish(D.result, best);
     }
-    publish(D.result, best);
 }
 
-// sum_xy |M_xy| of an n x m int32 matrix: the value of L_d when d >= n (every
-// row can take its own message, Eq. (L_o_norm)).  One block, int64 partials.
-__global__ __launch_bounds__(256) void k_sumabs(const int32_t* __restrict__ M, int64_t count,
-                                                int64_t* __restrict__ result)
+// sum_xy |M_xy| of int32 matrices, one block per matrix: the value of L_d when
+// d >= n (every row can take its own message, Eq. (L_o_norm)).  int64 partials.
+__global__ __launch_bounds__(256) void k_sumabs_many(const SumItem* __restrict__ items, uint32_t n)
 {
-    int64_t acc = 0;
-    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
-        const int64_t v = M[i];
-        acc += v < 0 ? -v : v;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     __shared__ int64_t part[4];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) *result = part[0] + part[1] + part[2] + part[3];
+    for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const SumItem si = items[b];
+        int64_t acc = 0;
+        for (int64_t i = threadIdx.x; i < si.count; i += blockDim.x) {
+            const int64_t v = si.M[i];
+            acc += v < 0 ? -v : v;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) *si.result = part[0] + part[1] + part[2] + part[3];
+        __syncthreads();
+    }
 }
 
-// out[i] = value for i < count (result slots start at INT64_MIN before a max)
-__global__ __launch_bounds__(256) void k_fill(int64_t* __restrict__ out, int64_t count, int64_t value)
+// Start of a run: result slots to INT64_MIN (a max follows), queue heads to 0.
+// A kernel rather than a memset so that captured graphs replay it correctly.
+__global__ __launch_bounds__(256) void k_reset(int64_t* __restrict__ results, uint32_t n_results,
+                                               uint32_t* __restrict__ heads, uint32_t n_heads)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) out[i] = value;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_results; i += stride) results[i] = INT64_MIN;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
 }
 
 namespace {
@@ -123,9 +144,9 @@ const void* kernel_dary64(int d, int mp)
     return g_dary64[d][mp / 4 - 1];
 }
 
-const void* kernel_sumabs() { return (const void*)&k_sumabs; }
+const void* kernel_sumabs_many() { return (const void*)&k_sumabs_many; }
 const void* kernel_wide() { return (const void*)&k_wide; }
-const void* kernel_fill() { return (const void*)&k_fill; }
+const void* kernel_reset() { return (const void*)&k_reset; }
 
 const void* lookup_bin32_kind0(int mp, int R);
 const void* lookup_bin32_kind1(int mp, int R);

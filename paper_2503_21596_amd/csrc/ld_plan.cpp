@@ -258,11 +258,17 @@ void choose_binary_shape(Plan& p, const SweepShape& sh, int F)
 {
     // F free rows beyond the R low rows
     const int Fp = F - p.R;
-    int P = std::min(Fp, sh.p_target);
-    int C = Fp - P;
-    if (C < sh.c_min) {
-        C = std::min(Fp, sh.c_min);
+    int P, C;
+    if (sh.c_target > 0) {
+        C = std::min(Fp, std::max(0, sh.c_target - p.R));
         P = Fp - C;
+    } else {
+        P = std::min(Fp, sh.p_target);
+        C = Fp - P;
+        if (C < sh.c_min) {
+            C = std::min(Fp, sh.c_min);
+            P = Fp - C;
+        }
     }
     if (C > 31) {
         C = 31;

@@ -16,6 +16,8 @@ struct SweepShape {
     int r_drop = 0;      // 1: one low row fewer than the register budget allows
     int dary_ptab = 8;   // restricted-growth prefix rows for d >= 3
     int dary_cwords = 4096;  // target d^C words per lane for d >= 3
+    int c_target = 0;        // > 0: binary prefixes of 2^c_target words (mid + low rows), the
+                             // rest of the rows become prefix rows (batch planning)
 };
 
 struct Plan {

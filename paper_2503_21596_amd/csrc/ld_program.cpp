@@ -1,0 +1,281 @@
+// Program builder and launcher (see ld_program.h).
+#include "ld_program.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "ld.h"
+#include "ld_registry.h"
+
+namespace ld {
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// VALU work of one word, for ordering items longest first (the exact constant
+// does not matter, only that it grows with the columns and the messages).
+double word_cost(const Plan& p)
+{
+    switch (p.kind) {
+    case PK_L1:
+    case PK_MARG: return p.m + 1.0;
+    case PK_L2: return 2.0 * p.m + 1.0;
+    case PK_LD: return 4.0 * p.m + p.d;
+    default: return 1.0;
+    }
+}
+
+int kind_of(const Plan& p)
+{
+    return p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
+}
+
+// descriptors and sum items as built: their pointers hold byte offsets into the
+// image until patch_program rebases them on a device address
+struct Rel {
+    std::vector<Desc> descs;
+    std::vector<SumItem> sums;
+};
+
+}  // namespace
+
+Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh)
+{
+    Program P;
+    const uint32_t n = (uint32_t)plans.size();
+    P.n_probs = n;
+    P.blob_off.assign(n, 0);
+    size_t off = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const Plan& p = *plans[i];
+        if (p.kind == PK_ZERO) {
+            P.zero.push_back((int)i);
+            continue;
+        }
+        P.blob_off[i] = off;
+        off = align256(off + p.blob.size());
+    }
+    P.off_descs = off;
+    off = align256(off + (size_t)n * sizeof(Desc));
+
+    // group the problems by sweep kernel; the sum-|M| problems go to one launch
+    std::map<std::pair<const void*, size_t>, std::vector<uint32_t>> groups;
+    std::vector<uint32_t> sums;
+    for (uint32_t i = 0; i < n; ++i) {
+        const Plan& p = *plans[i];
+        if (p.kind == PK_ZERO) continue;
+        if (p.kind == PK_SUMABS) {
+            sums.push_back(i);
+            continue;
+        }
+        groups[{p.kernel, p.wide ? (size_t)1 : (size_t)0}].push_back(i);
+    }
+
+    // items: per problem, ranges of prefixes; per group, longest first
+    std::vector<std::pair<Launch, std::vector<Item>>> launches;
+    uint32_t heads = 0;
+    for (auto& g : groups) {
+        Launch L;
+        L.kernel = g.first.first;
+        const bool wide = g.first.second != 0;
+        L.threads = wide ? 64 : 256;
+        std::vector<std::pair<double, Item>> its;
+        for (uint32_t i : g.second) {
+            const Plan& p = *plans[i];
+            L.lds = std::max(L.lds, p.lds);
+            const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);   // words per prefix
+            uint64_t per;
+            if (wide) {
+                per = 1;
+                if (sh.item_words > 0) per = (uint64_t)std::max(1.0, std::floor(sh.item_words / 64.0 / wpp));
+            } else {
+                per = sh.lanes_per_item;
+                if (sh.item_words > 0) {
+                    const double want = std::floor(sh.item_words / wpp / sh.lanes_per_item);
+                    per = (uint64_t)sh.lanes_per_item * (uint64_t)std::max(1.0, want);
+                }
+            }
+            per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
+            per = std::min<uint64_t>(per, 0xffffffffull);
+            for (uint64_t p0 = 0; p0 < p.n_prefix; p0 += per) {
+                Item it;
+                it.prob = i;
+                it.count = (uint32_t)std::min<uint64_t>(per, p.n_prefix - p0);
+                it.p0 = p0;
+                // a register-kernel wave covers 64 prefixes per round
+                const double rounds = wide ? it.count : std::ceil(it.count / 64.0);
+                its.push_back({rounds * wpp * word_cost(p), it});
+            }
+        }
+        std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        std::vector<Item> items;
+        items.reserve(its.size());
+        for (auto& c : its) {
+            L.cost += c.first;
+            items.push_back(c.second);
+        }
+        L.n_items = (uint32_t)items.size();
+        L.head = heads++;
+        launches.push_back({L, std::move(items)});
+    }
+    std::stable_sort(launches.begin(), launches.end(),
+                     [](const auto& a, const auto& b) { return a.first.cost > b.first.cost; });
+
+    P.off_items = off;
+    size_t ioff = 0;
+    for (auto& l : launches) {
+        l.first.off_items = P.off_items + ioff;
+        ioff += l.second.size() * sizeof(Item);
+    }
+    off = align256(off + ioff);
+    P.n_heads = heads;
+    P.off_heads = off;
+    off = align256(off + 4 * (size_t)std::max<uint32_t>(heads, 1));
+    P.off_results = off;
+    off = align256(off + 8 * (size_t)std::max<uint32_t>(n, 1));
+    P.n_sums = (uint32_t)sums.size();
+    P.off_sums = off;
+    off = align256(off + sizeof(SumItem) * (size_t)std::max<uint32_t>(P.n_sums, 1));
+
+    P.image.assign(off, 0);
+    Rel rel;
+    rel.descs.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const Plan& p = *plans[i];
+        if (p.kind == PK_ZERO) continue;
+        std::memcpy(P.image.data() + P.blob_off[i], p.blob.data(), p.blob.size());
+        Desc D{};
+        D.kind = kind_of(p);
+        D.m = p.m;
+        D.mp = p.mp;
+        D.d = p.d;
+        D.i64 = p.i64;
+        D.R = p.R;
+        D.C = p.C;
+        D.P = p.P;
+        D.P_tab = p.P_tab;
+        D.pfx_base = p.pfx_base;
+        D.n_prefix = p.n_prefix;
+        D.dpow_free = p.dpow_free;
+        D.base = (const void*)(uintptr_t)(P.blob_off[i] + p.off_base);
+        D.hid = (const void*)(uintptr_t)(P.blob_off[i] + p.off_hid);
+        D.mid = (const void*)(uintptr_t)(P.blob_off[i] + p.off_mid);
+        D.offs = (const void*)(uintptr_t)(P.blob_off[i] + p.off_offs);
+        D.tab = (const uint64_t*)(uintptr_t)(P.blob_off[i] + p.off_tab);
+        D.result = (int64_t*)(uintptr_t)(P.off_results + 8 * (size_t)i);
+        rel.descs[i] = D;
+    }
+    for (auto& l : launches) {
+        std::memcpy(P.image.data() + l.first.off_items, l.second.data(), l.second.size() * sizeof(Item));
+        P.launches.push_back(l.first);
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const int64_t v = INT64_MIN;
+        std::memcpy(P.image.data() + P.off_results + 8 * (size_t)i, &v, 8);
+    }
+    for (uint32_t j = 0; j < P.n_sums; ++j) {
+        const uint32_t i = sums[j];
+        SumItem si;
+        si.M = (const int32_t*)(uintptr_t)P.blob_off[i];
+        si.count = (int64_t)plans[i]->n * plans[i]->m;
+        si.result = (int64_t*)(uintptr_t)(P.off_results + 8 * (size_t)i);
+        rel.sums.push_back(si);
+    }
+    // relative descriptors are kept with the image bytes themselves: patching
+    // adds the device base to the stored offsets
+    for (uint32_t i = 0; i < n; ++i)
+        std::memcpy(P.image.data() + P.off_descs + i * sizeof(Desc), &rel.descs[i], sizeof(Desc));
+    for (uint32_t j = 0; j < P.n_sums; ++j)
+        std::memcpy(P.image.data() + P.off_sums + j * sizeof(SumItem), &rel.sums[j], sizeof(SumItem));
+    return P;
+}
+
+void patch_program(Program& P, void* dev)
+{
+    const uintptr_t old = (uintptr_t)P.dev;
+    const uintptr_t nb = (uintptr_t)dev;
+    auto fix = [&](auto& ptr) { ptr = (std::remove_reference_t<decltype(ptr)>)((uintptr_t)ptr - old + nb); };
+    for (uint32_t i = 0; i < P.n_probs; ++i) {
+        Desc D;
+        std::memcpy(&D, P.image.data() + P.off_descs + i * sizeof(Desc), sizeof(Desc));
+        if (D.result) {   // unused slots (problems with value 0) stay all-zero
+            fix(D.base);
+            fix(D.hid);
+            fix(D.mid);
+            fix(D.offs);
+            fix(D.tab);
+            fix(D.result);
+        }
+        std::memcpy(P.image.data() + P.off_descs + i * sizeof(Desc), &D, sizeof(Desc));
+    }
+    for (uint32_t j = 0; j < P.n_sums; ++j) {
+        SumItem si;
+        std::memcpy(&si, P.image.data() + P.off_sums + j * sizeof(SumItem), sizeof(SumItem));
+        fix(si.M);
+        fix(si.result);
+        std::memcpy(P.image.data() + P.off_sums + j * sizeof(SumItem), &si, sizeof(SumItem));
+    }
+    P.dev = dev;
+}
+
+uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void*, size_t>, uint32_t> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(kernel, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    uint32_t blocks = 1024;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)threads, lds) == hipSuccess &&
+        per_cu > 0)
+        blocks = (uint32_t)per_cu * (uint32_t)prop.multiProcessorCount;
+    cache[key] = blocks;
+    return blocks;
+}
+
+bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
+{
+    uint8_t* dev = (uint8_t*)P.dev;
+    int64_t* results = (int64_t*)(dev + P.off_results);
+    uint32_t* heads = (uint32_t*)(dev + P.off_heads);
+    uint32_t nr = P.n_probs, nh = P.n_heads;
+    {
+        const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(64, (std::max(nr, nh) + 255) / 256));
+        void* args[] = {(void*)&results, (void*)&nr, (void*)&heads, (void*)&nh};
+        if (hipLaunchKernel(kernel_reset(), dim3(blocks), dim3(256), args, 0, s) != hipSuccess) return false;
+    }
+    for (const Launch& L : P.launches) {
+        QArgs q{};
+        q.descs = (const Desc*)(dev + P.off_descs);
+        q.items = (const Item*)(dev + L.off_items);
+        q.n_items = L.n_items;
+        q.head = heads + L.head;
+        const uint32_t waves_per_block = L.threads / 64;
+        const uint32_t want = (L.n_items + waves_per_block - 1) / waves_per_block;
+        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, resident_blocks(L.kernel, L.threads, L.lds)));
+        void* args[] = {(void*)&q};
+        if (hipLaunchKernel(L.kernel, dim3(blocks), dim3(L.threads), args, L.lds, s) != hipSuccess) return false;
+    }
+    if (P.n_sums) {
+        const SumItem* items = (const SumItem*)(dev + P.off_sums);
+        uint32_t ns = P.n_sums;
+        void* args[] = {(void*)&items, (void*)&ns};
+        const uint32_t blocks = std::min<uint32_t>(ns, 1024);
+        if (hipLaunchKernel(kernel_sumabs_many(), dim3(blocks), dim3(256), args, 0, s) != hipSuccess) return false;
+    }
+    if (host_results && nr)
+        if (hipMemcpyAsync(host_results, results, 8 * (size_t)nr, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+    return true;
+}
+
+}  // namespace ld

@@ -1,0 +1,62 @@
+// A Program is everything needed to solve a set of planned problems on the GPU:
+// one device image (tables, descriptors, queue items, queue heads, result slots)
+// and the list of kernel launches over it.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "ld_plan.h"
+#include "ld_types.h"
+
+namespace ld {
+
+// one problem of k_sumabs_many: sum |M| of `count` int32 entries into *result
+struct SumItem {
+    const int32_t* M;
+    int64_t count;
+    int64_t* result;
+};
+
+struct Launch {
+    const void* kernel = nullptr;
+    uint32_t threads = 256;
+    uint32_t blocks = 1;
+    size_t lds = 0;
+    size_t off_items = 0;     // byte offset of this launch's items in the image
+    uint32_t n_items = 0;
+    uint32_t head = 0;        // index of this launch's queue head
+    double cost = 0;          // estimated VALU work, for ordering
+};
+
+struct Program {
+    std::vector<uint8_t> image;              // host copy of the device image
+    size_t off_descs = 0, off_items = 0, off_heads = 0, off_results = 0, off_sums = 0;
+    uint32_t n_probs = 0, n_heads = 0, n_sums = 0;
+    std::vector<size_t> blob_off;            // per problem, byte offset of its tables
+    std::vector<Launch> launches;
+    std::vector<int> zero;                   // problems whose value is 0 without a search
+    void* dev = nullptr;                     // device address the image was patched for
+};
+
+struct ItemShape {
+    uint32_t lanes_per_item = 64;   // prefixes per item for the register kernels
+    double item_words = 0;          // if > 0: grow items up to about this many words
+    uint32_t max_items = 1u << 20;  // per problem
+};
+
+// Build the image and launches for the given plans (all with status LD_OK).
+Program build_program(const std::vector<const Plan*>& plans, const ItemShape& shape);
+
+// Write device pointers into the image for a device buffer at `dev`.
+void patch_program(Program& prog, void* dev);
+
+// Enqueue: reset of heads and results, every launch, and the copy of the results
+// to host_results (pinned, n_probs int64).  Nothing here allocates.
+bool enqueue_program(const Program& prog, hipStream_t s, int64_t* host_results);
+
+// Blocks per launch that fill the device once for a kernel (occupancy x CUs).
+uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds);
+
+}  // namespace ld

@@ -37,10 +37,10 @@ const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
 const void* kernel_dary64(int d, int mp);
-const void* kernel_sumabs();
+const void* kernel_sumabs_many();
 const void* kernel_wide();
+const void* kernel_reset();
 constexpr size_t WIDE_LDS_MAX = 64 * 1024;   // bytes of state per wave
-const void* kernel_fill();
 
 // padded column count used for a problem with m columns
 inline int pad_bin32(int m) { return (m + 1) & ~1; }

@@ -184,10 +184,9 @@ struct Bin64 {
 #pragma unroll
         for (int y = 0; y < MP; ++y) s[y] = base[y];
         for (int h = 0; h < D.P; ++h) {
-            if ((v >> h) & 1u) {
+            const int64_t mask = -(int64_t)((v >> h) & 1u);
 #pragma unroll
-                for (int y = 0; y < MP; ++y) s[y] += hid[h * MP + y];
-            }
+            for (int y = 0; y < MP; ++y) s[y] += mask & hid[h * MP + y];
         }
         const uint64_t nsteps = 1ull << D.C;
         for (uint64_t t = 0;;) {
@@ -335,10 +334,11 @@ struct Dary64 {
             }
             cptr<int64_t> row = hid + h * MP;
 #pragma unroll
-            for (int k = 0; k < DD; ++k)
-                if (digit == (uint32_t)k)
+            for (int k = 0; k < DD; ++k) {
+                const int64_t mask = digit == (uint32_t)k ? -1 : 0;
 #pragma unroll
-                    for (int y = 0; y < MP; ++y) g[k][y] += row[y];
+                for (int y = 0; y < MP; ++y) g[k][y] += mask & row[y];
+            }
         }
         int64_t N[DD];
 #pragma unroll
@@ -378,6 +378,49 @@ struct Dary64 {
 };
 
 // ---------------------------------------------------------------------------
+// work queue
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint64_t uni64(uint64_t x)
+{
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+// The descriptor is the same for the whole wave: read it with scalar loads so its
+// fields, and every loop bound derived from them, live in SGPRs.
+__device__ __forceinline__ Desc load_desc(const Desc* p)
+{
+    static_assert(sizeof(Desc) % 4 == 0, "descriptor must be a whole number of dwords");
+    cptr<uint32_t> src = as_const<uint32_t>(p);
+    uint32_t w[sizeof(Desc) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Desc) / 4); ++i) w[i] = src[i];
+    Desc D;
+    __builtin_memcpy(&D, w, sizeof(Desc));
+    return D;
+}
+
+// Next item for this wave; false once the queue is exhausted, which every wave
+// reaches, so the grid always drains.  Every lane executes the atomic (lane 0
+// adds 1, the others 0) so that no lane-0-only branch precedes the readfirstlane
+// that broadcasts lane 0's old value: after such a branch the compiler may
+// re-enter the loop with lane 0 inactive, and readfirstlane would then read
+// another lane's stale value.
+__device__ __forceinline__ bool pop_item(const QArgs& q, Item& it)
+{
+    const uint32_t add = (threadIdx.x & 63) == 0 ? 1u : 0u;
+    uint32_t i = atomicAdd(q.head, add);
+    i = uni(i);
+    if (i >= q.n_items) return false;
+    cptr<uint32_t> w = as_const<uint32_t>(q.items) + 4 * (size_t)i;
+    it.prob = w[0];
+    it.count = w[1];
+    it.p0 = (uint64_t)w[2] | ((uint64_t)w[3] << 32);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // wave-level max and the per-problem result
 
 __device__ __forceinline__ int64_t wave_max(int64_t v)
@@ -390,11 +433,12 @@ __device__ __forceinline__ int64_t wave_max(int64_t v)
     return v;
 }
 
+// The wave max is the same in every lane, so every lane issues the atomic max
+// (no lane-0-only branch; see pop_item).
 __device__ __forceinline__ void publish(int64_t* result, int64_t v)
 {
     v = wave_max(v);
-    if ((threadIdx.x & 63) == 0)
-        __hip_atomic_fetch_max(result, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(result, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace ld

@@ -1,0 +1,254 @@
+// Autotuner: picks the sweep and queue shapes by timing candidates on a small
+// calibration set on the device at hand, then applies them to every later plan.
+// The paper found no general rule for its launch shapes and recommends timing a
+// smaller matrix first and reusing the result for larger ones (Sec. 4); this is
+// that procedure, automated.
+#include "ld_tune.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ld.h"
+#include "ld_api_internal.h"
+
+namespace ld {
+
+namespace {
+
+std::mutex g_mu;
+Tuning g_tuning;
+
+// SplitMix64, for the calibration matrices only
+struct Rng {
+    uint64_t s;
+    uint64_t next()
+    {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    int uniform(int lo, int hi) { return lo + (int)(next() % (uint64_t)(hi - lo + 1)); }
+};
+
+struct Cal {
+    std::vector<std::vector<int32_t>> mats;
+    std::vector<ld_problem> probs;
+};
+
+// a mixed set shaped like the batch workload, but small enough to time quickly
+Cal calibration_batch(int count, uint64_t seed)
+{
+    Cal c;
+    Rng r{seed};
+    c.mats.resize(count);
+    for (int i = 0; i < count; ++i) {
+        int d = r.uniform(1, 3);
+        const int marg = (d == 1 && r.uniform(0, 4) == 0) ? 1 : 0;
+        const int n = d == 3 ? r.uniform(10, 15) : r.uniform(12, 22);
+        const int m = r.uniform(8, 40);
+        auto& M = c.mats[i];
+        M.resize((size_t)n * m);
+        for (auto& v : M) v = r.uniform(-1000, 1000);
+        c.probs.push_back({M.data(), n, m, d, marg});
+    }
+    return c;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// best-of-three wall time of one batch with the current tuning
+double time_batch(const Cal& c)
+{
+    std::vector<int64_t> out(c.probs.size());
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+        const double t0 = now_s();
+        if (ld_norm_batch(c.probs.data(), (int32_t)c.probs.size(), out.data(), nullptr, nullptr) != LD_OK) return 1e30;
+        best = std::min(best, now_s() - t0);
+    }
+    return best;
+}
+
+double time_plain(const std::vector<int32_t>& M, int n, int m)
+{
+    double best = 1e30;
+    for (int rep = 0; rep < 3; ++rep) {
+        const double t0 = now_s();
+        if (ld_norm(M.data(), n, m, 1, 0) == INT64_MIN) return 1e30;
+        best = std::min(best, now_s() - t0);
+    }
+    return best;
+}
+
+bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
+{
+    FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    std::fprintf(f,
+                 "{\n  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
+                 "  \"plain_p_target\": %d,\n  \"plain_r_drop\": %d,\n  \"measured\": [%s]\n}\n",
+                 t.bin_c_target, t.dary_cwords, t.item_words, t.plain_p_target, t.plain_r_drop, notes.c_str());
+    std::fclose(f);
+    return true;
+}
+
+bool read_key(const std::string& text, const char* key, double* v)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t at = text.find(k);
+    if (at == std::string::npos) return false;
+    const size_t colon = text.find(':', at + k.size());
+    if (colon == std::string::npos) return false;
+    return std::sscanf(text.c_str() + colon + 1, "%lf", v) == 1;
+}
+
+}  // namespace
+
+Tuning get_tuning()
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    return g_tuning;
+}
+
+void set_tuning(const Tuning& t)
+{
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        g_tuning = t;
+    }
+    SweepShape s = get_shape();
+    s.p_target = t.plain_p_target;
+    s.r_drop = t.plain_r_drop;
+    set_shape(s);
+}
+
+SweepShape batch_shape_for(int n, int m, int d)
+{
+    (void)n;
+    (void)m;
+    const Tuning t = get_tuning();
+    SweepShape s = get_shape();
+    s.c_target = t.bin_c_target;
+    s.dary_cwords = t.dary_cwords;
+    (void)d;
+    return s;
+}
+
+ItemShape batch_item_shape()
+{
+    ItemShape s;
+    s.lanes_per_item = 64;
+    s.item_words = get_tuning().item_words;
+    return s;
+}
+
+}  // namespace ld
+
+using namespace ld;
+
+extern "C" {
+
+int ld_autotune(const char* path, double budget_seconds)
+{
+    if (!device_ok(nullptr)) {
+        set_error(LD_EHIP);
+        return LD_EHIP;
+    }
+    const double t_end = now_s() + std::max(1.0, budget_seconds);
+    const Tuning start = get_tuning();
+    Tuning best = start;
+    std::string notes;
+    char buf[160];
+
+    // batch shape: words per prefix (binary and d-ary) and words per queue item
+    const Cal cal = calibration_batch(384, 0x5eed);
+    double best_t = 1e30;
+    const int c_opts[] = {8, 10, 12, 14};
+    const double w_opts[] = {65536.0, 262144.0, 1048576.0};
+    for (int c : c_opts)
+        for (double w : w_opts) {
+            if (now_s() > t_end) break;
+            Tuning t = best;
+            t.bin_c_target = c;
+            t.dary_cwords = c <= 8 ? 729 : c <= 10 ? 2187 : c <= 12 ? 6561 : 19683;
+            t.item_words = w;
+            set_tuning(t);
+            const double dt = time_batch(cal);
+            std::snprintf(buf, sizeof buf, "%s{\"batch_c\": %d, \"item_words\": %.0f, \"ms\": %.3f}",
+                          notes.empty() ? "" : ", ", c, w, 1e3 * dt);
+            notes += buf;
+            if (dt < best_t) {
+                best_t = dt;
+                best = t;
+            }
+        }
+    set_tuning(best);
+
+    // plain calls: lanes (2^p_target) and low rows, timed on a 30 x 40 L1 problem
+    {
+        Rng r{0xca1};
+        const int n = 30, m = 40;
+        std::vector<int32_t> M((size_t)n * m);
+        for (auto& v : M) v = r.uniform(-100, 100);
+        double bt = 1e30;
+        Tuning bp = best;
+        for (int p : {16, 18, 20, 22})
+            for (int rd : {0, 1}) {
+                if (now_s() > t_end) break;
+                Tuning t = best;
+                t.plain_p_target = p;
+                t.plain_r_drop = rd;
+                set_tuning(t);
+                const double dt = time_plain(M, n, m);
+                std::snprintf(buf, sizeof buf, ", {\"plain_p\": %d, \"r_drop\": %d, \"ms\": %.3f}", p, rd, 1e3 * dt);
+                notes += buf;
+                if (dt < bt) {
+                    bt = dt;
+                    bp = t;
+                }
+            }
+        best = bp;
+    }
+    set_tuning(best);
+    if (path && *path && !write_tuning(path, best, notes)) {
+        set_error(LD_EINVAL);
+        return LD_EINVAL;
+    }
+    return LD_OK;
+}
+
+int ld_load_tuning(const char* path)
+{
+    FILE* f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) {
+        set_error(LD_EINVAL);
+        return LD_EINVAL;
+    }
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    Tuning t = get_tuning();
+    double v;
+    if (read_key(text, "bin_c_target", &v)) t.bin_c_target = std::max(0, std::min(40, (int)v));
+    if (read_key(text, "dary_cwords", &v)) t.dary_cwords = std::max(1, (int)v);
+    if (read_key(text, "item_words", &v)) t.item_words = std::max(1.0, v);
+    if (read_key(text, "plain_p_target", &v)) t.plain_p_target = std::max(0, std::min(40, (int)v));
+    if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
+    set_tuning(t);
+    return LD_OK;
+}
+
+}  // extern "C"

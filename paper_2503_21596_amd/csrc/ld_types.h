@@ -56,4 +56,21 @@ struct Desc {
     int64_t* result;
 };
 
+// One unit of a device work queue: prefixes [p0, p0 + count) of problem `prob`.
+struct Item {
+    uint32_t prob;
+    uint32_t count;
+    uint64_t p0;
+};
+
+// Arguments of every sweep kernel: waves pop items from `items` through the
+// atomic counter `head` until it passes n_items.
+struct QArgs {
+    const Desc* descs;
+    const Item* items;
+    uint32_t n_items;
+    uint32_t pad;
+    uint32_t* head;
+};
+
 }  // namespace ld
