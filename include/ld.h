@@ -44,6 +44,7 @@ extern "C" {
 #define LD_EBUSY 5       /* server: arena or queue full, retry later                     */
 #define LD_PENDING 6     /* server: result not ready yet                                  */
 #define LD_ENOTFOUND 7   /* server: unknown ticket                                        */
+#define LD_ECANCELED 8   /* server: request cancelled before it completed                 */
 
 /* ld_norm -- L1 / L_marg / L_d of one matrix (definitions above).
  * Preprocessing keeps the value exactly: all-zero rows and columns are dropped
@@ -125,6 +126,50 @@ void ld_release(ld_prepared* h);
 /* Error code of the calling thread's last failed call, and its text. */
 int ld_last_error(void);
 const char* ld_error_string(int code);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of L_d solves on one GPU.
+ *
+ * A scheduler thread owns the device.  Requests are admitted while the arena
+ * (device bytes for their tables) and the in-flight slots allow; each admitted
+ * problem's tables are uploaded once and its prefix space is cut into queue
+ * items.  The scheduler issues short steps -- queue launches over items chosen
+ * smallest-remaining-work first, about step_ms of device work each, at most two
+ * steps in flight -- so a request that arrives while others run joins at the next
+ * step.  Partial maxima stay in device result slots between steps; a request is
+ * complete when all its items have run.  Values equal ld_norm's. */
+typedef struct {
+    uint64_t arena_bytes;           /* device bytes for problem tables (0: 256 MiB)        */
+    int32_t max_inflight_problems;  /* result slots (0: 1024)                              */
+    int32_t max_items_per_launch;   /* cap on one step's items (0: 65536)                  */
+    double words_per_item;          /* queue-item size (0: the tuned batch value)           */
+    double step_ms;                 /* device work per step (0: 4 ms)                       */
+    int32_t max_queued;             /* submitted but not admitted; beyond: LD_EBUSY (0: 65536) */
+    int32_t device;                 /* HIP device index                                     */
+} ld_server_config;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, launches, items;
+    int32_t inflight, queued;
+    double p50_ms, p99_ms, mean_ms;  /* latency: submit -> completion seen by the scheduler */
+} ld_stats;
+
+typedef struct ld_server ld_server;
+/* NULL on error (ld_last_error). cfg may be NULL for the defaults. */
+ld_server* ld_server_create(const ld_server_config* cfg);
+/* Copies M; plans on the calling thread.  *ticket identifies the request.  Returns
+ * LD_OK, LD_EBUSY (queue full; nothing stored), or a planning error (the ticket
+ * then completes at once with that error). */
+int ld_server_submit(ld_server* s, const ld_problem* p, uint64_t* ticket);
+/* LD_PENDING until the request completes; then its status (LD_OK: *value set).
+ * A completed ticket can be read any number of times until the server is destroyed. */
+int ld_server_poll(ld_server* s, uint64_t ticket, int64_t* value);
+int ld_server_wait(ld_server* s, uint64_t ticket, int64_t* value);
+/* Cancel a queued or in-flight request (its remaining items are dropped). */
+int ld_server_cancel(ld_server* s, uint64_t ticket);
+void ld_server_stats(ld_server* s, ld_stats* out);
+/* Drains in-flight steps, stops the scheduler, frees the device memory. */
+void ld_server_destroy(ld_server* s);
 
 /* ---------------------------------------------------------------------------
  * Introspection (host only, never touches the GPU). */

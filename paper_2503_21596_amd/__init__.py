@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libld.so")
 INT64_MIN = -(1 << 63)
 
-LD_OK, LD_EINVAL, LD_EMARG_D, LD_ETOOBIG, LD_EHIP, LD_EBUSY, LD_PENDING, LD_ENOTFOUND = range(8)
+LD_OK, LD_EINVAL, LD_EMARG_D, LD_ETOOBIG, LD_EHIP, LD_EBUSY, LD_PENDING, LD_ENOTFOUND, LD_ECANCELED = range(9)
 
 PLAN_KINDS = {0: "L1", 1: "L_marg", 2: "L2", 3: "L_d", 4: "sum|M|", 5: "zero"}
 
@@ -43,7 +43,7 @@ class ld_plan_info(ctypes.Structure):
 class ld_server_config(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight_problems", ctypes.c_int32),
                 ("max_items_per_launch", ctypes.c_int32), ("words_per_item", ctypes.c_double),
-                ("device", ctypes.c_int32)]
+                ("step_ms", ctypes.c_double), ("max_queued", ctypes.c_int32), ("device", ctypes.c_int32)]
 
 
 class ld_stats(ctypes.Structure):
@@ -76,6 +76,13 @@ SIGNATURES = {
     "ld_batch_run": (ctypes.c_int, [_P, _P, _P]),
     "ld_batch_last_ms": (ctypes.c_float, [_P]),
     "ld_batch_release": (None, [_P]),
+    "ld_server_create": (_P, [_P]),
+    "ld_server_submit": (ctypes.c_int, [_P, _P, _P]),
+    "ld_server_poll": (ctypes.c_int, [_P, _U64, _P]),
+    "ld_server_wait": (ctypes.c_int, [_P, _U64, _P]),
+    "ld_server_cancel": (ctypes.c_int, [_P, _U64]),
+    "ld_server_stats": (None, [_P, _P]),
+    "ld_server_destroy": (None, [_P]),
     "ld_autotune": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double]),
     "ld_load_tuning": (ctypes.c_int, [ctypes.c_char_p]),
 }
@@ -274,20 +281,23 @@ def load_tuning(path: str) -> None:
 class Server:
     """Continuous-batching request server (ld_server_* in include/ld.h)."""
 
-    def __init__(self, arena_bytes: int = 64 << 20, max_inflight_problems: int = 256,
-                 max_items_per_launch: int = 4096, words_per_item: float = 0.0, device: int = 0):
+    def __init__(self, arena_bytes: int = 256 << 20, max_inflight_problems: int = 1024,
+                 max_items_per_launch: int = 65536, words_per_item: float = 0.0, step_ms: float = 0.0,
+                 max_queued: int = 0, device: int = 0):
         cfg = ld_server_config(arena_bytes, max_inflight_problems, max_items_per_launch, words_per_item,
-                               device)
+                               step_ms, max_queued, device)
         self._h = lib().ld_server_create(ctypes.byref(cfg))
         if not self._h:
             raise _err()
-        self._keep = {}
 
-    def submit(self, M, d: int = 1, marginals: int = 0) -> int:
+    def submit(self, M, d: int = 1, marginals: int = 0, check: bool = True):
+        """Returns the ticket; with check=False returns (rc, ticket) and never raises."""
         a = _mat(M)
         p = ld_problem(a.ctypes.data, a.shape[0], a.shape[1], int(d), int(marginals))
         t = ctypes.c_uint64()
         rc = lib().ld_server_submit(self._h, ctypes.byref(p), ctypes.byref(t))
+        if not check:
+            return rc, int(t.value)
         if rc != LD_OK:
             raise _err(rc)
         return int(t.value)
@@ -301,9 +311,12 @@ class Server:
             raise _err(rc)
         return int(v.value)
 
-    def wait(self, ticket: int) -> int:
+    def wait(self, ticket: int, check: bool = True):
+        """The value; with check=False returns (rc, value) and never raises."""
         v = ctypes.c_int64()
         rc = lib().ld_server_wait(self._h, ticket, ctypes.byref(v))
+        if not check:
+            return rc, int(v.value)
         if rc != LD_OK:
             raise _err(rc)
         return int(v.value)

@@ -96,6 +96,32 @@ __global__ __launch_bounds__(256) void k_reset(int64_t* __restrict__ results, ui
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
 }
 
+// Server steps: copy newly admitted tables and descriptors from the step's
+// upload buffer to their arena / descriptor slots, one block per copy job.
+__global__ __launch_bounds__(256) void k_scatter(const ScatterOp* __restrict__ ops, uint32_t n)
+{
+    for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const ScatterOp op = ops[b];
+        if ((((uintptr_t)op.src | (uintptr_t)op.dst | op.bytes) & 15) == 0) {
+            const uint4* src = (const uint4*)op.src;
+            uint4* dst = (uint4*)op.dst;
+            for (uint64_t i = threadIdx.x; i < op.bytes / 16; i += blockDim.x) dst[i] = src[i];
+        } else {
+            for (uint64_t i = threadIdx.x; i < op.bytes; i += blockDim.x) op.dst[i] = op.src[i];
+        }
+    }
+}
+
+// Server steps: result slots of newly admitted problems to INT64_MIN, the step's
+// queue heads to 0.
+__global__ __launch_bounds__(256) void k_reset_slots(int64_t* __restrict__ results, const uint32_t* __restrict__ slots,
+                                                     uint32_t n_slots, uint32_t* __restrict__ heads, uint32_t n_heads)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += stride) results[slots[i]] = INT64_MIN;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
+}
+
 namespace {
 
 constexpr int NMPD = MAX_MP / 4;   // mp = 4, 8, ..., 64
@@ -147,6 +173,8 @@ const void* kernel_dary64(int d, int mp)
 const void* kernel_sumabs_many() { return (const void*)&k_sumabs_many; }
 const void* kernel_wide() { return (const void*)&k_wide; }
 const void* kernel_reset() { return (const void*)&k_reset; }
+const void* kernel_scatter() { return (const void*)&k_scatter; }
+const void* kernel_reset_slots() { return (const void*)&k_reset_slots; }
 
 const void* lookup_bin32_kind0(int mp, int R);
 const void* lookup_bin32_kind1(int mp, int R);

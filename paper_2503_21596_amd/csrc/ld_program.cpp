@@ -17,19 +17,6 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// VALU work of one word, for ordering items longest first (the exact constant
-// does not matter, only that it grows with the columns and the messages).
-double word_cost(const Plan& p)
-{
-    switch (p.kind) {
-    case PK_L1:
-    case PK_MARG: return p.m + 1.0;
-    case PK_L2: return 2.0 * p.m + 1.0;
-    case PK_LD: return 4.0 * p.m + p.d;
-    default: return 1.0;
-    }
-}
-
 int kind_of(const Plan& p)
 {
     return p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
@@ -43,6 +30,47 @@ struct Rel {
 };
 
 }  // namespace
+
+// VALU work of one word, for ordering items longest first (the exact constant
+// does not matter, only that it grows with the columns and the messages).
+double word_cost(const Plan& p)
+{
+    switch (p.kind) {
+    case PK_L1:
+    case PK_MARG: return p.m + 1.0;
+    case PK_L2: return 2.0 * p.m + 1.0;
+    case PK_LD: return 4.0 * p.m + p.d;
+    default: return 1.0;
+    }
+}
+
+void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<std::pair<double, Item>>& out)
+{
+    const bool wide = p.wide != 0;
+    const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);   // words per prefix
+    uint64_t per;
+    if (wide) {
+        per = 1;
+        if (sh.item_words > 0) per = (uint64_t)std::max(1.0, std::floor(sh.item_words / 64.0 / wpp));
+    } else {
+        per = sh.lanes_per_item;
+        if (sh.item_words > 0) {
+            const double want = std::floor(sh.item_words / wpp / sh.lanes_per_item);
+            per = (uint64_t)sh.lanes_per_item * (uint64_t)std::max(1.0, want);
+        }
+    }
+    per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
+    per = std::min<uint64_t>(per, 0xffffffffull);
+    for (uint64_t p0 = 0; p0 < p.n_prefix; p0 += per) {
+        Item it;
+        it.prob = prob;
+        it.count = (uint32_t)std::min<uint64_t>(per, p.n_prefix - p0);
+        it.p0 = p0;
+        // a register-kernel wave covers 64 prefixes per round
+        const double rounds = wide ? it.count : std::ceil(it.count / 64.0);
+        out.push_back({rounds * wpp * word_cost(p), it});
+    }
+}
 
 Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh)
 {
@@ -82,35 +110,11 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
     for (auto& g : groups) {
         Launch L;
         L.kernel = g.first.first;
-        const bool wide = g.first.second != 0;
-        L.threads = wide ? 64 : 256;
+        L.threads = g.first.second != 0 ? 64 : 256;
         std::vector<std::pair<double, Item>> its;
         for (uint32_t i : g.second) {
-            const Plan& p = *plans[i];
-            L.lds = std::max(L.lds, p.lds);
-            const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);   // words per prefix
-            uint64_t per;
-            if (wide) {
-                per = 1;
-                if (sh.item_words > 0) per = (uint64_t)std::max(1.0, std::floor(sh.item_words / 64.0 / wpp));
-            } else {
-                per = sh.lanes_per_item;
-                if (sh.item_words > 0) {
-                    const double want = std::floor(sh.item_words / wpp / sh.lanes_per_item);
-                    per = (uint64_t)sh.lanes_per_item * (uint64_t)std::max(1.0, want);
-                }
-            }
-            per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
-            per = std::min<uint64_t>(per, 0xffffffffull);
-            for (uint64_t p0 = 0; p0 < p.n_prefix; p0 += per) {
-                Item it;
-                it.prob = i;
-                it.count = (uint32_t)std::min<uint64_t>(per, p.n_prefix - p0);
-                it.p0 = p0;
-                // a register-kernel wave covers 64 prefixes per round
-                const double rounds = wide ? it.count : std::ceil(it.count / 64.0);
-                its.push_back({rounds * wpp * word_cost(p), it});
-            }
+            L.lds = std::max(L.lds, plans[i]->lds);
+            split_items(*plans[i], i, sh, its);
         }
         std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         std::vector<Item> items;

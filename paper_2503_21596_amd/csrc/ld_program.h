@@ -46,6 +46,21 @@ struct ItemShape {
     uint32_t max_items = 1u << 20;  // per problem
 };
 
+// Split one problem's prefix space into queue items (tagged with problem index
+// `prob`), each with its estimated VALU cost.  `wide` items are swept by one wave
+// prefix after prefix; register-kernel items put one prefix on each lane.
+void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<std::pair<double, Item>>& out);
+
+// estimated VALU operations per word of a planned problem
+double word_cost(const Plan& p);
+
+// copy jobs for k_scatter: bytes from src to dst, both device-visible
+struct ScatterOp {
+    const uint8_t* src;
+    uint8_t* dst;
+    uint64_t bytes;
+};
+
 // Build the image and launches for the given plans (all with status LD_OK).
 Program build_program(const std::vector<const Plan*>& plans, const ItemShape& shape);
 

@@ -40,6 +40,8 @@ const void* kernel_dary64(int d, int mp);
 const void* kernel_sumabs_many();
 const void* kernel_wide();
 const void* kernel_reset();
+const void* kernel_scatter();
+const void* kernel_reset_slots();
 constexpr size_t WIDE_LDS_MAX = 64 * 1024;   // bytes of state per wave
 
 // padded column count used for a problem with m columns

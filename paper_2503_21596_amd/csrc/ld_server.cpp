@@ -1,0 +1,675 @@
+// Request server: continuous batching of L_d solves on one GPU (see include/ld.h).
+//
+// Submitting threads plan their request and queue it.  One scheduler thread owns
+// the device.  Each scheduler step:
+//   1. retires finished steps: a request whose items have all run is complete,
+//      and its value is read from the result copy of the step that ran its last
+//      items;
+//   2. admits queued requests while a result slot and arena bytes are free;
+//   3. picks items, smallest remaining work first, up to about step_ms of
+//      device work;
+//   4. enqueues: one upload of the step buffer (new tables, descriptors, items),
+//      a scatter kernel, a slot and head reset, one persistent queue launch per
+//      kernel shape, and the copy of all result slots to pinned memory.
+// At most two steps are in flight, so a request that arrives while others run is
+// swept in the next step.  Result slots keep partial maxima between steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ld.h"
+#include "ld_api_internal.h"
+#include "ld_plan.h"
+#include "ld_program.h"
+#include "ld_registry.h"
+#include "ld_tune.h"
+
+using namespace ld;
+
+namespace {
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// sustained VALU rate used to size a step (ops/s); only the step length depends on it
+constexpr double STEP_OPS_PER_S = 3.0e13;
+
+struct Request {
+    uint64_t ticket = 0;
+    Plan plan;
+    double t_submit = 0, t_done = 0;
+    int status = LD_PENDING;
+    int64_t value = 0;
+    // scheduling state
+    int slot = -1;
+    size_t arena_off = 0, arena_size = 0;
+    std::vector<Item> items;         // sorted longest first
+    std::vector<double> cost;
+    size_t next = 0;                 // first item not yet issued
+    double remaining = 0;            // estimated cost of the items not yet issued
+    uint32_t outstanding = 0;        // issued items whose step has not retired
+    bool uploaded = false;
+    bool canceled = false;
+    bool is_sum = false;
+};
+
+// first-fit allocator over [0, size)
+struct Arena {
+    std::map<size_t, size_t> free_;   // offset -> bytes
+    explicit Arena(size_t size = 0) { if (size) free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Step {
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    uint8_t* host = nullptr;      // pinned upload buffer
+    uint8_t* dev = nullptr;       // device copy of it
+    int64_t* hres = nullptr;      // pinned copy of every result slot after the step
+    std::vector<std::pair<Request*, uint32_t>> issued;   // request, items in this step
+};
+
+}  // namespace
+
+struct ld_server {
+    ld_server_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint8_t* arena_dev = nullptr;
+    Desc* d_descs = nullptr;
+    int64_t* d_results = nullptr;
+    size_t step_bytes = 0;
+    Step steps[2];
+    int next_step = 0;
+    Arena arena;
+    std::vector<int> free_slots;
+    std::vector<Request*> slots;
+
+    std::mutex mu;
+    std::condition_variable cv;       // scheduler wake-up
+    std::condition_variable done_cv;  // request completion
+    std::deque<Request*> pending;
+    std::unordered_map<uint64_t, Request*> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    bool failed = false;
+    std::thread worker;
+
+    uint64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_launches = 0, st_items = 0;
+    std::vector<double> latencies_ms;
+
+    ~ld_server()
+    {
+        for (auto& s : steps) {
+            if (s.ev) (void)hipEventDestroy(s.ev);
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.dev) (void)hipFree(s.dev);
+            if (s.hres) (void)hipHostFree(s.hres);
+        }
+        if (arena_dev) (void)hipFree(arena_dev);
+        if (d_descs) (void)hipFree(d_descs);
+        if (d_results) (void)hipFree(d_results);
+        if (stream) (void)hipStreamDestroy(stream);
+        for (auto& kv : all) delete kv.second;
+    }
+};
+
+namespace {
+
+// complete a request (mu held)
+void finish(ld_server* S, Request* r, int status, int64_t value)
+{
+    r->status = status;
+    r->value = value;
+    r->t_done = now_s();
+    if (status == LD_OK) {
+        S->st_completed++;
+        S->latencies_ms.push_back(1e3 * (r->t_done - r->t_submit));
+    }
+    r->plan = Plan{};   // keep only the outcome
+    r->items.clear();
+    r->items.shrink_to_fit();
+    r->cost.clear();
+    r->cost.shrink_to_fit();
+    S->done_cv.notify_all();
+}
+
+void release_slot(ld_server* S, Request* r)
+{
+    if (r->slot >= 0) {
+        S->slots[r->slot] = nullptr;
+        S->free_slots.push_back(r->slot);
+        r->slot = -1;
+    }
+    if (r->arena_size) {
+        S->arena.release(r->arena_off, r->arena_size);
+        r->arena_size = 0;
+    }
+}
+
+// Retire the oldest busy step if it has finished (wait: block until it has).
+bool retire(ld_server* S, bool wait)
+{
+    for (int k = 0; k < 2; ++k) {
+        Step& st = S->steps[(S->next_step + k) % 2];
+        if (!st.busy) continue;
+        if (wait) {
+            if (hipEventSynchronize(st.ev) != hipSuccess) return false;
+        } else {
+            const hipError_t q = hipEventQuery(st.ev);
+            if (q == hipErrorNotReady) return true;
+            if (q != hipSuccess) return false;
+        }
+        std::lock_guard<std::mutex> g(S->mu);
+        for (auto& [r, n] : st.issued) {
+            r->outstanding -= n;
+            if (r->outstanding == 0 && r->next >= r->items.size()) {
+                const int slot = r->slot;
+                const int64_t v = st.hres[slot];
+                release_slot(S, r);
+                finish(S, r, r->canceled ? LD_ECANCELED : LD_OK, v);
+            }
+        }
+        st.issued.clear();
+        st.busy = false;
+        return true;
+    }
+    return true;
+}
+
+int busy_steps(ld_server* S) { return (int)S->steps[0].busy + (int)S->steps[1].busy; }
+
+// Build and enqueue one step on S->steps[S->next_step].  Returns false on a HIP error.
+bool issue_step(ld_server* S, bool* issued_any)
+{
+    *issued_any = false;
+    Step& st = S->steps[S->next_step];
+    if (st.busy) return true;
+    const int max_slots = S->cfg.max_inflight_problems;
+    std::vector<Request*> admitted;
+    std::vector<std::pair<Request*, std::vector<Item>>> picks;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        // 2. admission by slot and arena space (FIFO; a request too big for the
+        // free arena waits and holds back the ones behind it)
+        while (!S->pending.empty() && !S->free_slots.empty()) {
+            Request* r = S->pending.front();
+            const size_t bytes = align256(std::max<size_t>(r->plan.blob.size(), 256));
+            size_t off;
+            if (!S->arena.alloc(bytes, &off)) break;
+            S->pending.pop_front();
+            r->arena_off = off;
+            r->arena_size = bytes;
+            r->slot = S->free_slots.back();
+            S->free_slots.pop_back();
+            S->slots[r->slot] = r;
+            admitted.push_back(r);
+        }
+        // 3. items: smallest remaining work first, up to the step budget
+        std::vector<Request*> live;
+        for (Request* r : S->slots)
+            if (r && r->next < r->items.size()) live.push_back(r);
+        std::sort(live.begin(), live.end(), [](Request* a, Request* b) { return a->remaining < b->remaining; });
+        const double budget = STEP_OPS_PER_S * S->cfg.step_ms * 1e-3;
+        double used = 0;
+        size_t n_items = 0;
+        for (Request* r : live) {
+            if (used >= budget || n_items >= (size_t)S->cfg.max_items_per_launch) break;
+            std::vector<Item> take;
+            while (r->next < r->items.size() && (take.empty() || used < budget) &&
+                   n_items < (size_t)S->cfg.max_items_per_launch) {
+                Item it = r->items[r->next];
+                it.prob = (uint32_t)r->slot;
+                used += r->cost[r->next];
+                r->remaining -= r->cost[r->next];
+                ++r->next;
+                take.push_back(it);
+                ++n_items;
+            }
+            if (!take.empty()) {
+                r->outstanding += (uint32_t)take.size();
+                picks.push_back({r, std::move(take)});
+            }
+        }
+        // sum-|M| requests run once, in the step that admits them
+        for (Request* r : admitted)
+            if (r->is_sum) {
+                r->outstanding += 1;
+                picks.push_back({r, {}});
+            }
+    }
+    if (admitted.empty() && picks.empty()) return true;
+
+    // layout of the step buffer: scatter ops, new tables, new descriptors, reset
+    // slots, items (grouped by kernel), sum items
+    std::map<std::pair<const void*, size_t>, std::vector<Item>> groups;
+    std::map<std::pair<const void*, size_t>, size_t> group_lds;
+    std::vector<SumItem> sums;
+    for (auto& [r, items] : picks) {
+        if (r->is_sum) {
+            SumItem si;
+            si.M = (const int32_t*)(S->arena_dev + r->arena_off);
+            si.count = (int64_t)r->plan.n * r->plan.m;
+            si.result = S->d_results + r->slot;
+            sums.push_back(si);
+            continue;
+        }
+        auto key = std::make_pair(r->plan.kernel, (size_t)(r->plan.wide ? 1 : 0));
+        auto& v = groups[key];
+        v.insert(v.end(), items.begin(), items.end());
+        group_lds[key] = std::max(group_lds[key], r->plan.lds);
+    }
+    size_t off = 0;
+    const size_t off_ops = off;
+    off = align256(off + sizeof(ScatterOp) * 2 * admitted.size());
+    std::vector<size_t> blob_at(admitted.size()), desc_at(admitted.size());
+    for (size_t k = 0; k < admitted.size(); ++k) {
+        blob_at[k] = off;
+        off = align256(off + admitted[k]->plan.blob.size());
+    }
+    for (size_t k = 0; k < admitted.size(); ++k) {
+        desc_at[k] = off;
+        off = align256(off + sizeof(Desc));
+    }
+    const size_t off_slots = off;
+    off = align256(off + 4 * admitted.size());
+    std::vector<std::pair<size_t, size_t>> gpos;   // items offset, count per group
+    for (auto& g : groups) {
+        gpos.push_back({off, g.second.size()});
+        off = align256(off + sizeof(Item) * g.second.size());
+    }
+    const size_t off_heads = off;
+    off = align256(off + 4 * std::max<size_t>(groups.size(), 1));
+    const size_t off_sums = off;
+    off = align256(off + sizeof(SumItem) * sums.size());
+    if (off > S->step_bytes) {
+        // cannot happen with the admission limits below; refuse rather than overflow
+        return false;
+    }
+
+    uint8_t* H = st.host;
+    uint8_t* D = st.dev;
+    std::vector<ScatterOp> ops;
+    for (size_t k = 0; k < admitted.size(); ++k) {
+        Request* r = admitted[k];
+        std::memcpy(H + blob_at[k], r->plan.blob.data(), r->plan.blob.size());
+        ops.push_back({D + blob_at[k], S->arena_dev + r->arena_off, (uint64_t)r->plan.blob.size()});
+        const Plan& p = r->plan;
+        const uint8_t* base = S->arena_dev + r->arena_off;
+        Desc d{};
+        d.kind = p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
+        d.m = p.m;
+        d.mp = p.mp;
+        d.d = p.d;
+        d.i64 = p.i64;
+        d.R = p.R;
+        d.C = p.C;
+        d.P = p.P;
+        d.P_tab = p.P_tab;
+        d.pfx_base = p.pfx_base;
+        d.n_prefix = p.n_prefix;
+        d.dpow_free = p.dpow_free;
+        d.base = base + p.off_base;
+        d.hid = base + p.off_hid;
+        d.mid = base + p.off_mid;
+        d.offs = base + p.off_offs;
+        d.tab = (const uint64_t*)(base + p.off_tab);
+        d.result = S->d_results + r->slot;
+        std::memcpy(H + desc_at[k], &d, sizeof(Desc));
+        ops.push_back({D + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
+        const uint32_t slot = (uint32_t)r->slot;
+        std::memcpy(H + off_slots + 4 * k, &slot, 4);
+    }
+    if (!ops.empty()) std::memcpy(H + off_ops, ops.data(), sizeof(ScatterOp) * ops.size());
+    size_t gi = 0;
+    for (auto& g : groups) {
+        std::memcpy(H + gpos[gi].first, g.second.data(), sizeof(Item) * g.second.size());
+        ++gi;
+    }
+    std::memset(H + off_heads, 0, 4 * std::max<size_t>(groups.size(), 1));
+    if (!sums.empty()) std::memcpy(H + off_sums, sums.data(), sizeof(SumItem) * sums.size());
+
+    // 4. enqueue
+    hipStream_t s = S->stream;
+    bool ok = hipMemcpyAsync(D, H, off, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (ok && !ops.empty()) {
+        const ScatterOp* dops = (const ScatterOp*)(D + off_ops);
+        uint32_t nops = (uint32_t)ops.size();
+        void* args[] = {(void*)&dops, (void*)&nops};
+        ok = hipLaunchKernel(kernel_scatter(), dim3(std::min<uint32_t>(nops, 1024)), dim3(256), args, 0, s) ==
+             hipSuccess;
+    }
+    uint32_t* dheads = (uint32_t*)(D + off_heads);
+    if (ok && !admitted.empty()) {
+        const uint32_t* dslots = (const uint32_t*)(D + off_slots);
+        uint32_t ns = (uint32_t)admitted.size(), nh = 0;
+        int64_t* dres = S->d_results;
+        void* args[] = {(void*)&dres, (void*)&dslots, (void*)&ns, (void*)&dheads, (void*)&nh};
+        ok = hipLaunchKernel(kernel_reset_slots(), dim3(std::max<uint32_t>(1, std::min<uint32_t>(64, (ns + 255) / 256))),
+                             dim3(256), args, 0, s) == hipSuccess;
+    }
+    gi = 0;
+    size_t n_items = 0;
+    for (auto& g : groups) {
+        QArgs q{};
+        q.descs = S->d_descs;
+        q.items = (const Item*)(D + gpos[gi].first);
+        q.n_items = (uint32_t)gpos[gi].second;
+        q.head = dheads + gi;
+        const uint32_t threads = g.first.second ? 64 : 256;
+        const size_t lds = group_lds[g.first];
+        const uint32_t want = (q.n_items + threads / 64 - 1) / (threads / 64);
+        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, resident_blocks(g.first.first, threads, lds)));
+        void* args[] = {(void*)&q};
+        ok = ok && hipLaunchKernel(g.first.first, dim3(blocks), dim3(threads), args, lds, s) == hipSuccess;
+        n_items += q.n_items;
+        ++gi;
+    }
+    if (ok && !sums.empty()) {
+        const SumItem* ds = (const SumItem*)(D + off_sums);
+        uint32_t n = (uint32_t)sums.size();
+        void* args[] = {(void*)&ds, (void*)&n};
+        ok = hipLaunchKernel(kernel_sumabs_many(), dim3(std::min<uint32_t>(n, 1024)), dim3(256), args, 0, s) ==
+             hipSuccess;
+    }
+    ok = ok && hipMemcpyAsync(st.hres, S->d_results, 8 * (size_t)max_slots, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipEventRecord(st.ev, s) == hipSuccess;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        for (auto& [r, items] : picks) st.issued.push_back({r, r->is_sum ? 1u : (uint32_t)items.size()});
+        S->st_launches += groups.size() + (sums.empty() ? 0 : 1);
+        S->st_items += n_items;
+    }
+    st.busy = true;
+    S->next_step = 1 - S->next_step;
+    *issued_any = true;
+    return ok;
+}
+
+void scheduler(ld_server* S)
+{
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        bool have_work;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            auto work_left = [&]() {
+                if (!S->pending.empty() && !S->free_slots.empty()) return true;
+                for (Request* r : S->slots)
+                    if (r && r->next < r->items.size()) return true;
+                return false;
+            };
+            if (busy_steps(S) == 0) {
+                S->cv.wait(lk, [&]() { return S->stop || work_left(); });
+                if (S->stop && !work_left()) return;
+            }
+            have_work = work_left();
+        }
+        if (!retire(S, false)) break;
+        bool issued = false;
+        if (have_work && busy_steps(S) < 2) {
+            if (!issue_step(S, &issued)) break;
+        }
+        if (!issued && busy_steps(S) > 0) {
+            if (!retire(S, true)) break;
+        }
+    }
+    // a HIP failure: fail everything still open
+    std::lock_guard<std::mutex> g(S->mu);
+    S->failed = true;
+    for (auto& kv : S->all)
+        if (kv.second->status == LD_PENDING) finish(S, kv.second, LD_EHIP, INT64_MIN);
+}
+
+}  // namespace
+
+extern "C" {
+
+ld_server* ld_server_create(const ld_server_config* cfg_in)
+{
+    ld_server_config cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    if (!cfg.arena_bytes) cfg.arena_bytes = (uint64_t)256 << 20;
+    if (cfg.max_inflight_problems <= 0) cfg.max_inflight_problems = 1024;
+    if (cfg.max_items_per_launch <= 0) cfg.max_items_per_launch = 65536;
+    if (cfg.words_per_item <= 0) cfg.words_per_item = get_tuning().item_words;
+    if (cfg.step_ms <= 0) cfg.step_ms = 4.0;
+    if (cfg.max_queued <= 0) cfg.max_queued = 65536;
+    ld_server* S = new ld_server;
+    S->cfg = cfg;
+    S->device = cfg.device;
+    int count = 0;
+    bool ok = hipGetDeviceCount(&count) == hipSuccess && cfg.device >= 0 && cfg.device < count &&
+              hipSetDevice(cfg.device) == hipSuccess && device_ok(nullptr);
+    ok = ok && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMalloc((void**)&S->arena_dev, cfg.arena_bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&S->d_descs, sizeof(Desc) * cfg.max_inflight_problems) == hipSuccess;
+    ok = ok && hipMalloc((void**)&S->d_results, 8 * (size_t)cfg.max_inflight_problems) == hipSuccess;
+    // a step uploads at most every slot's tables and descriptors plus its items
+    S->step_bytes = align256(sizeof(ScatterOp) * 2 * cfg.max_inflight_problems) + cfg.arena_bytes +
+                    align256(256 + sizeof(Desc)) * (size_t)cfg.max_inflight_problems +
+                    align256(4 * (size_t)cfg.max_inflight_problems) +
+                    align256(sizeof(Item) * (size_t)cfg.max_items_per_launch) + 256 * 64 +
+                    align256(sizeof(SumItem) * (size_t)cfg.max_inflight_problems) + (1 << 16);
+    for (auto& st : S->steps) {
+        ok = ok && hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&st.host, S->step_bytes, hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipMalloc((void**)&st.dev, S->step_bytes) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&st.hres, 8 * (size_t)cfg.max_inflight_problems, hipHostMallocDefault) ==
+                       hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        delete S;
+        set_error(LD_EHIP);
+        return nullptr;
+    }
+    S->arena = Arena(cfg.arena_bytes);
+    S->slots.assign(cfg.max_inflight_problems, nullptr);
+    for (int i = cfg.max_inflight_problems - 1; i >= 0; --i) S->free_slots.push_back(i);
+    S->worker = std::thread(scheduler, S);
+    return S;
+}
+
+int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
+{
+    if (!S || !p || !ticket) {
+        set_error(LD_EINVAL);
+        return LD_EINVAL;
+    }
+    Request* r = new Request;
+    r->t_submit = now_s();
+    r->plan = make_plan(p->M, p->n, p->m, p->d, p->marginals, batch_shape_for(p->n, p->m, p->d));
+    if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO) {
+        if (r->plan.kind == PK_SUMABS) {
+            r->is_sum = true;
+        } else {
+            ItemShape sh;
+            sh.item_words = S->cfg.words_per_item;
+            std::vector<std::pair<double, Item>> its;
+            split_items(r->plan, 0, sh, its);
+            std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+            for (auto& c : its) {
+                r->items.push_back(c.second);
+                r->cost.push_back(c.first);
+                r->remaining += c.first;
+            }
+        }
+        if (align256(r->plan.blob.size()) > S->cfg.arena_bytes) r->plan.status = LD_ETOOBIG;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->failed) {
+        delete r;
+        set_error(LD_EHIP);
+        return LD_EHIP;
+    }
+    if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO && (int)S->pending.size() >= S->cfg.max_queued) {
+        delete r;
+        S->st_rejected++;
+        set_error(LD_EBUSY);
+        return LD_EBUSY;
+    }
+    r->ticket = S->next_ticket++;
+    *ticket = r->ticket;
+    S->all[r->ticket] = r;
+    S->st_submitted++;
+    if (r->plan.status != LD_OK) {
+        const int st = r->plan.status;
+        finish(S, r, st, INT64_MIN);
+        set_error(st);
+        return st;
+    }
+    if (r->plan.kind == PK_ZERO) {
+        finish(S, r, LD_OK, 0);
+        return LD_OK;
+    }
+    S->pending.push_back(r);
+    S->cv.notify_one();
+    return LD_OK;
+}
+
+int ld_server_poll(ld_server* S, uint64_t ticket, int64_t* value)
+{
+    if (!S) return LD_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return LD_ENOTFOUND;
+    if (it->second->status == LD_PENDING) return LD_PENDING;
+    if (value && it->second->status == LD_OK) *value = it->second->value;
+    return it->second->status;
+}
+
+int ld_server_wait(ld_server* S, uint64_t ticket, int64_t* value)
+{
+    if (!S) return LD_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return LD_ENOTFOUND;
+    Request* r = it->second;
+    S->done_cv.wait(lk, [&]() { return r->status != LD_PENDING; });
+    if (value && r->status == LD_OK) *value = r->value;
+    return r->status;
+}
+
+int ld_server_cancel(ld_server* S, uint64_t ticket)
+{
+    if (!S) return LD_EINVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return LD_ENOTFOUND;
+    Request* r = it->second;
+    if (r->status != LD_PENDING) return r->status;
+    auto q = std::find(S->pending.begin(), S->pending.end(), r);
+    if (q != S->pending.end()) {
+        S->pending.erase(q);
+        finish(S, r, LD_ECANCELED, INT64_MIN);
+        return LD_OK;
+    }
+    // in flight: drop the items not yet issued; it completes when its issued
+    // items have retired
+    r->canceled = true;
+    r->remaining = 0;
+    r->next = r->items.size();
+    if (r->outstanding == 0) {
+        release_slot(S, r);
+        finish(S, r, LD_ECANCELED, INT64_MIN);
+    }
+    return LD_OK;
+}
+
+void ld_server_stats(ld_server* S, ld_stats* out)
+{
+    if (!S || !out) return;
+    std::lock_guard<std::mutex> g(S->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = S->st_submitted;
+    out->completed = S->st_completed;
+    out->rejected = S->st_rejected;
+    out->launches = S->st_launches;
+    out->items = S->st_items;
+    out->queued = (int32_t)S->pending.size();
+    for (Request* r : S->slots)
+        if (r) out->inflight++;
+    if (!S->latencies_ms.empty()) {
+        std::vector<double> v = S->latencies_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double q) { return v[std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5))]; };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double s = 0;
+        for (double x : v) s += x;
+        out->mean_ms = s / v.size();
+    }
+}
+
+void ld_server_destroy(ld_server* S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        // queued requests are cancelled; in-flight ones finish their issued items
+        while (!S->pending.empty()) {
+            Request* r = S->pending.front();
+            S->pending.pop_front();
+            finish(S, r, LD_ECANCELED, INT64_MIN);
+        }
+        for (Request* r : S->slots) {
+            if (!r) continue;
+            r->canceled = true;
+            r->next = r->items.size();
+            r->remaining = 0;
+            if (r->outstanding == 0) {   // admitted, nothing issued: done now
+                release_slot(S, r);
+                finish(S, r, LD_ECANCELED, INT64_MIN);
+            }
+        }
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    delete S;
+}
+
+}  // extern "C"
