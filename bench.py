@@ -73,6 +73,74 @@ def cpu_baseline(M, target_s: float = 12.0):
                       f"(last {q} rows fixed per prefix), {dt:.1f} s, {threads} threads"}
 
 
+def bench_batch(L, synth, seed: int = 0):
+    """The 4096-problem batch: one ld_norm_batch call, a prepared batch replayed from its
+    HIP graph, and 4096 separate ld_norm calls; solves/s for each (wall clock)."""
+    probs = synth.batch_problems(seed, count=4096)
+    t0 = time.perf_counter()
+    out = L.ld_norm_batch(probs)
+    t_batch = time.perf_counter() - t0
+    B = L.Batch(probs)
+    B.run()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        rep = B.run()
+    t_replay = (time.perf_counter() - t0) / reps
+    dev_ms = B.last_ms()
+    B.close()
+    t0 = time.perf_counter()
+    plain = [L.ld_norm(M, d, marg) for M, d, marg in probs]
+    t_plain = time.perf_counter() - t0
+    n = len(probs)
+    return {"problems": n, "batch_solves_per_s": n / t_batch, "replay_solves_per_s": n / t_replay,
+            "plain_solves_per_s": n / t_plain, "batch_s": t_batch, "replay_s": t_replay,
+            "replay_device_ms": dev_ms, "plain_s": t_plain,
+            "speedup_vs_plain": t_plain / t_batch,
+            "identical": bool(list(out) == plain and list(rep) == plain)}
+
+
+def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0):
+    """Poisson request stream into the server (continuous batching) against the same
+    trace served by sequential plain calls (FIFO; queueing from the measured
+    service times)."""
+    import numpy as np
+    reqs = synth.served_requests(seed, count=count, rate=rate)
+    S = L.Server()
+    tickets = []
+    t_start = time.perf_counter()
+    for t_arr, M, d in reqs:
+        delay = t_start + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(S.submit(M, d, 0))
+    vals = [S.wait(t) for t in tickets]
+    t_end = time.perf_counter()
+    st = S.stats()
+    S.close()
+    served = {"requests": count, "rate_per_s": rate, "solves_per_s": count / (t_end - t_start),
+              "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+              "launches": st["launches"]}
+    # sequential plain calls: service times, then a FIFO queue over the arrival times
+    durs = []
+    seq_vals = []
+    for _, M, d in reqs:
+        t0 = time.perf_counter()
+        seq_vals.append(L.ld_norm(M, d, 0))
+        durs.append(time.perf_counter() - t0)
+    free_at = 0.0
+    lat = []
+    for (t_arr, _, _), dur in zip(reqs, durs):
+        start = max(t_arr, free_at)
+        free_at = start + dur
+        lat.append(free_at - t_arr)
+    lat = np.array(lat) * 1e3
+    seq = {"solves_per_s": count / max(free_at, reqs[-1][0]), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "busy_s": float(sum(durs))}
+    return {"served": served, "sequential_plain": seq, "identical": vals == seq_vals,
+            "offered_load_of_sequential": float(sum(durs)) / reqs[-1][0]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +227,10 @@ def main():
     }
 
     if not a.no_extras:
+        print("bench: batch", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = bench_batch(L, synth)
+        print("bench: serve", file=sys.stderr, flush=True)
+        out["served"] = bench_serve(L, synth)
         Mm = synth.config_42_marg(0)
         hm = L.Prepared(Mm, 1, 1)
         vm = hm.run(stream)

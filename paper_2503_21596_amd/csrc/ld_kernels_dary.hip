@@ -13,16 +13,24 @@ namespace ld {
 template <int MP, int DD>
 __global__ __launch_bounds__(256) void k_dary32(QArgs q)
 {
+    constexpr int R = dary_r(MP, DD);
+    using K = Dary32<MP, DD, R>;
     const uint32_t lane = threadIdx.x & 63;
+    uint32_t off[K::NO][MP];
+    uint32_t loaded = 0xffffffffu;
     Item it;
     while (pop_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
+        if (it.prob != loaded) {
+            K::load_offs(D, off);
+            loaded = it.prob;
+        }
         uint32_t best = 0;
         const uint32_t rounds = (it.count + 63) >> 6;
         for (uint32_t j = 0; j < rounds; ++j) {
             uint32_t i = lane + 64 * j;
             if (i >= it.count) i = it.count - 1;
-            Dary32<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, best);
+            K::prefix(D, D.pfx_base + it.p0 + i, off, best);
         }
         publish(D.result, (int64_t)best);
     }

@@ -2,6 +2,7 @@
 #include "ld_plan.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 
@@ -168,20 +169,24 @@ void build_binary(Plan& p, const Mat& A)
 }
 
 // d-ary tables.  Row roles in A: P_tab prefix rows covered by tab[], then P
-// plain prefix rows, then C mid rows; `fixed0`: row 0 is fixed at message 0
-// instead (range plans), the remaining rows follow it.
+// plain prefix rows, then C mid rows, then R low rows; `fixed0`: row 0 comes
+// first and is fixed at message 0 (range plans).  The low rows are not part of
+// any state vector: offs[S] = 2^31 - (sum of the low rows in subset S) lets the
+// kernel score every message choice of the low rows against the same state.
 void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fixed0)
 {
-    const int m = A.m, mp = p.mp, C = p.C;
+    const int m = A.m, mp = p.mp, C = p.C, R = p.R;
     const int nh = p.P_tab + p.P;
     const int h0 = fixed0 ? 1 : 0;          // first prefix row
     const int mid0 = h0 + nh;
+    const int low0 = mid0 + C;
+    const int NS = 1 << R;
     const size_t es = p.i64 ? 8 : 4;
     p.off_base = 0;
     p.off_hid = align256(es * (size_t)mp);
     p.off_mid = align256(p.off_hid + es * (size_t)std::max(nh, 1) * mp);
-    p.off_tab = align256(p.off_mid + es * (size_t)std::max(C, 1) * mp);
-    p.off_offs = p.off_tab;
+    p.off_offs = align256(p.off_mid + es * (size_t)std::max(C, 1) * mp);
+    p.off_tab = align256(p.off_offs + 4 * (size_t)NS * mp);
     const size_t end = align256(p.off_tab + 8 * std::max<size_t>(tab.size(), 1));
     p.blob.assign(end, 0);
     for (int y = 0; y < mp; ++y) {
@@ -202,6 +207,14 @@ void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fi
     };
     for (int h = 0; h < nh; ++h) row(p.off_hid, h, h0 + h);
     for (int c = 0; c < C; ++c) row(p.off_mid, c, mid0 + c);
+    for (int sub = 0; sub < NS; ++sub)
+        for (int y = 0; y < mp; ++y) {
+            int64_t low = 0;
+            if (y < m)
+                for (int i = 0; i < R; ++i)
+                    if ((sub >> i) & 1) low += A.at(low0 + i, y);
+            put<uint32_t>(p.blob, p.off_offs, (size_t)sub * mp + y, (uint32_t)(BIAS - low));
+        }
     for (size_t i = 0; i < tab.size(); ++i) put<uint64_t>(p.blob, p.off_tab, i, tab[i]);
 }
 
@@ -417,11 +430,13 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
         p.status = LD_ETOOBIG;
         return p;
     }
+    // the register kernel scores R low rows per state; the others walk every row
+    p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
     // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
     // row is fixed (message 0), which is the paper's fix-one-entry reduction
-    p.P_tab = d <= 16 ? std::min(A.n, std::max(1, std::min(16, sh.dary_ptab))) : 1;
+    p.P_tab = d <= 16 ? std::min(A.n - p.R, std::max(1, std::min(16, sh.dary_ptab))) : 1;
     while (p.P_tab > 1 && rgs_count(p.P_tab, d) > (double)(1 << 20)) --p.P_tab;
-    const int rest = A.n - p.P_tab;
+    const int rest = A.n - p.P_tab - p.R;
     int C = 0;
     {
         uint64_t w = 1;
@@ -430,19 +445,33 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
             ++C;
         }
     }
+    int P = rest - C;
+    // a single problem should fill the device: trade mid rows for prefix rows
+    // (more lanes, fewer words each) while few lanes exist, keeping two mid rows
+    if (sh.dary_lanes > 0) {
+        auto lanes = [&](int pt, int pf) { return rgs_count(pt, d) * std::pow((double)d, pf); };
+        while (C > 2 && lanes(p.P_tab, P) < (double)sh.dary_lanes) {
+            if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)(1 << 20))
+                ++p.P_tab;
+            else
+                ++P;
+            --C;
+        }
+    }
     p.C = C;
-    p.P = rest - C;
+    p.P = P;
     std::vector<uint64_t> tab;
     rgs(p.P_tab, d, tab);
     bool of = false;
     p.dpow_free = upow(d, p.P, &of);
     const uint64_t cw = upow(d, C, &of);
-    if (of || (double)tab.size() * (double)p.dpow_free * (double)cw > (double)WORD_LIMIT) {
+    if (of || (double)tab.size() * (double)p.dpow_free * (double)cw * std::pow((double)d, p.R) >
+                  (double)WORD_LIMIT) {
         p.status = LD_ETOOBIG;
         return p;
     }
     p.n_prefix = (uint64_t)tab.size() * p.dpow_free;
-    p.words = (double)p.n_prefix * (double)cw;
+    p.words = (double)p.n_prefix * (double)cw * std::pow((double)d, p.R);
     p.M = A.a;
     build_dary(p, A, tab, false);
     return p;
@@ -526,21 +555,25 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
         p.status = LD_ETOOBIG;
         return p;
     }
-    const uint64_t cw = upow(d, free_rows, &of);
+    p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    // rows 1..n-q-1 give the C mid rows and the R low rows (zero rows pad them when
+    // there are fewer than R: a zero row changes no message sum)
+    const int lowmid = std::max(free_rows, p.R);
+    const uint64_t cw = upow(d, lowmid - p.R, &of);
     if (of || cw > 0xffffffffull) {
         p.status = LD_ETOOBIG;
         return p;
     }
     p.P_tab = 0;
     p.P = q;
-    p.C = free_rows;
+    p.C = lowmid - p.R;
     p.dpow_free = npfx;
-    p.words = (double)p.n_prefix * (double)cw;
-    // B: row 0, then the q prefix rows, then the mid rows
+    p.words = (double)p.n_prefix * (double)cw * std::pow((double)d, p.R);
+    // B: row 0, then the q prefix rows, then the mid and low rows
     Mat B;
-    B.n = n;
+    B.n = 1 + q + lowmid;
     B.m = m;
-    B.a.assign((size_t)n * m, 0);
+    B.a.assign((size_t)B.n * m, 0);
     for (int y = 0; y < m; ++y) B.a[y] = A.at(0, y);
     for (int i = 0; i < q; ++i)
         for (int y = 0; y < m; ++y) B.a[(size_t)(1 + i) * m + y] = A.at(n - q + i, y);

@@ -18,6 +18,8 @@ struct SweepShape {
     int dary_cwords = 4096;  // target d^C words per lane for d >= 3
     int c_target = 0;        // > 0: binary prefixes of 2^c_target words (mid + low rows), the
                              // rest of the rows become prefix rows (batch planning)
+    int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
+                               // lanes exist (0: keep dary_cwords words per lane)
 };
 
 struct Plan {

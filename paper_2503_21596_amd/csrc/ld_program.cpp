@@ -110,6 +110,23 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
     for (auto& g : groups) {
         Launch L;
         L.kernel = g.first.first;
+        if (g.second.size() == 1 && n == 1) {
+            // a single problem: equal items, computed on the device from their index
+            const Plan& p = *plans[g.second[0]];
+            L.threads = g.first.second != 0 ? 64 : 256;
+            L.lds = p.lds;
+            L.implicit = true;
+            L.prob = g.second[0];
+            uint64_t per = p.wide ? 1 : sh.lanes_per_item;
+            per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
+            L.per = per;
+            L.n_prefix = p.n_prefix;
+            L.n_items = (uint32_t)((p.n_prefix + per - 1) / per);
+            L.head = heads++;
+            L.cost = p.words * word_cost(p);
+            launches.push_back({L, {}});
+            continue;
+        }
         L.threads = g.first.second != 0 ? 64 : 256;
         std::vector<std::pair<double, Item>> its;
         for (uint32_t i : g.second) {
@@ -260,9 +277,12 @@ bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
     for (const Launch& L : P.launches) {
         QArgs q{};
         q.descs = (const Desc*)(dev + P.off_descs);
-        q.items = (const Item*)(dev + L.off_items);
+        q.items = L.implicit ? nullptr : (const Item*)(dev + L.off_items);
         q.n_items = L.n_items;
         q.head = heads + L.head;
+        q.prob = L.prob;
+        q.per = L.per;
+        q.n_prefix = L.n_prefix;
         const uint32_t waves_per_block = L.threads / 64;
         const uint32_t want = (L.n_items + waves_per_block - 1) / waves_per_block;
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, resident_blocks(L.kernel, L.threads, L.lds)));

@@ -28,6 +28,10 @@ struct Launch {
     uint32_t n_items = 0;
     uint32_t head = 0;        // index of this launch's queue head
     double cost = 0;          // estimated VALU work, for ordering
+    bool implicit = false;    // items computed on the device (one problem)
+    uint32_t prob = 0;        // implicit items: the problem
+    uint64_t per = 0;         // implicit items: prefixes per item
+    uint64_t n_prefix = 0;    // implicit items: prefixes of the problem
 };
 
 struct Program {

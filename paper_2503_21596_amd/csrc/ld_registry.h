@@ -28,6 +28,15 @@ constexpr int bin_rmax(int mp, int kind)
 // d-ary: d vectors of mp columns
 constexpr bool dary_fits(int mp, int d) { return d * mp <= 192; }
 
+// d-ary low rows scored per state: the largest R <= 2 whose 2^R - 1 subset
+// operands fit beside the d state vectors, (d + 2^R - 1) * mp <= 200
+constexpr int dary_r(int mp, int d)
+{
+    for (int r = 2; r >= 1; --r)
+        if ((d + (1 << r) - 1) * mp <= 200) return r;
+    return 0;
+}
+
 struct KernelRef {
     const void* fn = nullptr;   // __global__ function
 };

@@ -392,7 +392,7 @@ bool issue_step(ld_server* S, bool* issued_any)
     gi = 0;
     size_t n_items = 0;
     for (auto& g : groups) {
-        QArgs q{};
+        QArgs q{};   // explicit items (several problems per launch)
         q.descs = S->d_descs;
         q.items = (const Item*)(D + gpos[gi].first);
         q.n_items = (uint32_t)gpos[gi].second;

@@ -208,13 +208,22 @@ struct Bin64 {
 // d-ary kind (d >= 3): one column-sum vector per message, updated by the two-slot
 // rule of Eq. (update2); only the two touched message norms are recomputed.
 
-template <int MP, int DD>
+// The R low rows are not walked: for every message k the lane keeps
+// X[k][S] = || g_k + (sum of the low rows in subset S) ||_1 for every subset S of
+// the low rows (S = 0 is the plain norm).  A word of the block fixes the messages
+// w of the low rows; its score is T + sum over the messages k that receive low
+// rows of (X[k][S_k(w)] - X[k][0]), T = sum_k X[k][0].  A mid step changes two
+// messages, so only their 2^R entries are recomputed, and the best of the d^R
+// words of the block is a small max over message choices.
+template <int MP, int DD, int R>
 struct Dary32 {
-    __device__ static __forceinline__ uint32_t norm(const uint32_t (&g)[MP], uint32_t bias)
+    static constexpr int NS = 1 << R;   // subsets of the low rows
+
+    __device__ static __forceinline__ uint32_t norm(const uint32_t (&g)[MP], const uint32_t (&o)[MP])
     {
         uint32_t acc = 0;
 #pragma unroll
-        for (int y = 0; y < MP; ++y) acc = sad_u32(g[y], bias, acc);
+        for (int y = 0; y < MP; ++y) acc = sad_u32(g[y], o[y], acc);
         return acc;
     }
 
@@ -224,7 +233,65 @@ struct Dary32 {
         for (int y = 0; y < MP; ++y) g[y] += mask & (uint32_t)row[y];
     }
 
-    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, uint32_t& best)
+    // operand of subset S >= 1: 2^31 - (sum of the low rows in S), so that
+    // |g - o| = |true g + low sum|; the empty subset uses the single bias 2^31
+    static constexpr int NO = NS > 1 ? NS - 1 : 1;
+    __device__ static __forceinline__ void load_offs(const Desc& D, uint32_t (&off)[NO][MP])
+    {
+        cptr<uint32_t> o = as_const<uint32_t>(D.offs);
+#pragma unroll
+        for (int s = 1; s < NS; ++s)
+#pragma unroll
+            for (int y = 0; y < MP; ++y) off[s - 1][y] = in_vgpr(o[s * MP + y]);
+    }
+
+    __device__ static __forceinline__ uint32_t norm0(const uint32_t (&g)[MP], uint32_t bias)
+    {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int y = 0; y < MP; ++y) acc = sad_u32(g[y], bias, acc);
+        return acc;
+    }
+
+    __device__ static __forceinline__ void refresh(const uint32_t (&g)[MP], const uint32_t (&off)[NO][MP],
+                                                   uint32_t bias, uint32_t (&X)[NS])
+    {
+        X[0] = norm0(g, bias);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) X[s] = norm(g, off[s - 1]);
+    }
+
+    // best score of the d^R words of the block
+    __device__ static __forceinline__ uint32_t block(const uint32_t (&X)[DD][NS])
+    {
+        uint32_t T = 0;
+#pragma unroll
+        for (int k = 0; k < DD; ++k) T += X[k][0];
+        if constexpr (R == 0) {
+            return T;
+        } else if constexpr (R == 1) {
+            int32_t b = (int32_t)(X[0][1] - X[0][0]);
+#pragma unroll
+            for (int k = 1; k < DD; ++k) b = max(b, (int32_t)(X[k][1] - X[k][0]));
+            return T + (uint32_t)b;
+        } else {
+            // both low rows on one message k: X[k][3]; on two messages k != l:
+            // X[k][1] - X[k][0] + X[l][2] - X[l][0]
+            int32_t b = (int32_t)(X[0][3] - X[0][0]);
+#pragma unroll
+            for (int k = 1; k < DD; ++k) b = max(b, (int32_t)(X[k][3] - X[k][0]));
+#pragma unroll
+            for (int k = 0; k < DD; ++k)
+#pragma unroll
+                for (int l = 0; l < DD; ++l)
+                    if (k != l)
+                        b = max(b, (int32_t)(X[k][1] - X[k][0]) + (int32_t)(X[l][2] - X[l][0]));
+            return T + (uint32_t)b;
+        }
+    }
+
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, const uint32_t (&off)[NO][MP],
+                                                  uint32_t& best)
     {
         cptr<uint32_t> base = as_const<uint32_t>(D.base);
         cptr<int32_t> hid = as_const<int32_t>(D.hid);
@@ -236,7 +303,7 @@ struct Dary32 {
 #pragma unroll
         for (int k = 1; k < DD; ++k)
 #pragma unroll
-            for (int y = 0; y < MP; ++y) g[k][y] = bias;
+            for (int y = 0; y < MP; ++y) g[k][y] = 0x80000000u;
 
         uint64_t code = 0, fr = v;
         if (D.P_tab > 0) {
@@ -257,13 +324,10 @@ struct Dary32 {
 #pragma unroll
             for (int k = 0; k < DD; ++k) add_row(g[k], digit == (uint32_t)k ? 0xffffffffu : 0u, row);
         }
-        uint32_t N[DD];
+        uint32_t X[DD][NS];
 #pragma unroll
-        for (int k = 0; k < DD; ++k) N[k] = norm(g[k], bias);
-        uint32_t total = 0;
-#pragma unroll
-        for (int k = 0; k < DD; ++k) total += N[k];
-        best = max(best, total);
+        for (int k = 0; k < DD; ++k) refresh(g[k], off, bias, X[k]);
+        best = max(best, block(X));
 
         uint32_t nsteps = 1;
         for (int c = 0; c < D.C; ++c) nsteps *= DD;
@@ -276,7 +340,7 @@ struct Dary32 {
                 if ((uint32_t)k == from) {
 #pragma unroll
                     for (int y = 0; y < MP; ++y) g[k][y] -= (uint32_t)row[y];
-                    N[k] = norm(g[k], bias);
+                    refresh(g[k], off, bias, X[k]);
                 }
             }
 #pragma unroll
@@ -284,13 +348,10 @@ struct Dary32 {
                 if ((uint32_t)k == to) {
 #pragma unroll
                     for (int y = 0; y < MP; ++y) g[k][y] += (uint32_t)row[y];
-                    N[k] = norm(g[k], bias);
+                    refresh(g[k], off, bias, X[k]);
                 }
             }
-            total = 0;
-#pragma unroll
-            for (int k = 0; k < DD; ++k) total += N[k];
-            best = max(best, total);
+            best = max(best, block(X));
         }
     }
 };
@@ -413,6 +474,13 @@ __device__ __forceinline__ bool pop_item(const QArgs& q, Item& it)
     uint32_t i = atomicAdd(q.head, add);
     i = uni(i);
     if (i >= q.n_items) return false;
+    if (q.items == nullptr) {
+        it.prob = q.prob;
+        it.p0 = (uint64_t)i * q.per;
+        const uint64_t left = q.n_prefix - it.p0;
+        it.count = (uint32_t)(left < q.per ? left : q.per);
+        return true;
+    }
     cptr<uint32_t> w = as_const<uint32_t>(q.items) + 4 * (size_t)i;
     it.prob = w[0];
     it.count = w[1];

@@ -141,6 +141,7 @@ SweepShape batch_shape_for(int n, int m, int d)
     SweepShape s = get_shape();
     s.c_target = t.bin_c_target;
     s.dary_cwords = t.dary_cwords;
+    s.dary_lanes = 0;   // many problems share the device: keep the tuned words per lane
     (void)d;
     return s;
 }

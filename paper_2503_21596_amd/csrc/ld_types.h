@@ -63,14 +63,18 @@ struct Item {
     uint64_t p0;
 };
 
-// Arguments of every sweep kernel: waves pop items from `items` through the
-// atomic counter `head` until it passes n_items.
+// Arguments of every sweep kernel: waves pop items through the atomic counter
+// `head` until it passes n_items.  With items == nullptr the items are implicit:
+// item i covers prefixes [i * per, min((i + 1) * per, n_prefix)) of problem
+// `prob` (one problem swept evenly, nothing to build or upload).
 struct QArgs {
     const Desc* descs;
     const Item* items;
     uint32_t n_items;
-    uint32_t pad;
+    uint32_t prob;
     uint32_t* head;
+    uint64_t per;
+    uint64_t n_prefix;
 };
 
 }  // namespace ld

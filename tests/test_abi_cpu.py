@@ -91,13 +91,25 @@ def test_plan_int64_boundary():
     assert L.plan(M2, 1, 0)["i64"] == 1
 
 
+def stirling2_upto(n, d):
+    """sum_{k <= d} S(n, k): the number of restricted-growth strings of length n
+    with at most d distinct digits (assignments of n rows to d messages up to
+    relabelling the messages)."""
+    S = [1] + [0] * d
+    for _ in range(n):
+        S = [0] + [k * S[k] + S[k - 1] for k in range(1, d + 1)]
+    return sum(S)
+
+
 def test_plan_dary_counts():
-    # restricted-growth prefixes: 16 rows, d = 3 -> 1094 strings of length 8 times 3^8
-    p = L.plan(synth.config_pm(0), 3, 0)
-    assert p["kind_name"] == "L_d" and p["P_tab"] == 8
-    assert p["words"] == 1094 * 3 ** 8
-    p = L.plan(synth.config_pm(0), 4, 0)
-    assert p["words"] == 2795 * 4 ** 8
+    # restricted-growth prefixes of length P_tab, then free digits: every class of
+    # assignments up to message relabelling is covered at least once
+    for d in (3, 4):
+        p = L.plan(synth.config_pm(0), d, 0)
+        assert p["kind_name"] == "L_d" and p["P_tab"] >= 1
+        assert p["words"] == stirling2_upto(p["P_tab"], d) * d ** (16 - p["P_tab"])
+        assert stirling2_upto(16, d) <= p["words"] <= d ** 15
+    assert stirling2_upto(8, 3) == 1094 and stirling2_upto(8, 4) == 2795
     # d >= rows: the value is sum |M|, no search
     assert L.plan(synth.matrix(0, 3, 4, -3, 3, "abi"), 3, 0)["kind_name"] in ("sum|M|",)
 
