@@ -120,7 +120,7 @@ int64_t run_plan_sync(const Plan& p)
     }
     if (p.kind == PK_ZERO) return 0;
     int64_t v = INT64_MIN;
-    if (!run_plans_sync({&p}, ItemShape{}, &v, nullptr)) {
+    if (!run_plans_sync({&p}, plain_item_shape(), &v, nullptr)) {
         set_error(LD_EHIP);
         return INT64_MIN;
     }
@@ -199,7 +199,7 @@ ld_prepared* ld_prepare(const int32_t* M, int32_t n, int32_t m, int32_t d, int32
         delete h;
         return nullptr;
     }
-    h->prog = build_program({&h->plan}, ItemShape{});
+    h->prog = build_program({&h->plan}, plain_item_shape());
     bool ok = device_ok(&h->device);
     ok = ok && hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreate(&h->e0) == hipSuccess && hipEventCreate(&h->e1) == hipSuccess;

@@ -12,25 +12,22 @@
 
 namespace ld {
 
-// Persistent queue kernel: each wave pops items (problem, prefix range); lane l
+// Persistent queue kernel: each wave takes items (problem, prefix range); lane l
 // of the wave takes prefixes p0 + l, p0 + l + 64, ... of the item.  Lanes past
 // the item's end repeat its last prefix, which cannot change a maximum, so the
-// wave stays converged.  The low-row operands are reloaded only when the
-// problem changes between consecutive items.
+// wave stays converged.  The low-row operands are reloaded, and the running max
+// published, only when the problem changes between consecutive items.
 template <int MP, int KIND, int R>
 __global__ __launch_bounds__(256) void k_bin32(QArgs q)
 {
     using B = Bin32<MP, KIND, R>;
     const uint32_t lane = threadIdx.x & 63;
     uint32_t off[B::K][B::NW][MP];
-    uint32_t loaded = 0xffffffffu;
+    WaveBest wb;
     Item it;
-    while (pop_item(q, it)) {
+    while (next_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
-        if (it.prob != loaded) {
-            B::load_offs(D, off);
-            loaded = it.prob;
-        }
+        if (wb.enter(it.prob, D.result)) B::load_offs(D, off);
         uint32_t best = B::best_init();
         const uint32_t rounds = (it.count + 63) >> 6;
         for (uint32_t j = 0; j < rounds; ++j) {
@@ -38,8 +35,9 @@ __global__ __launch_bounds__(256) void k_bin32(QArgs q)
             if (i >= it.count) i = it.count - 1;
             B::prefix(D, D.pfx_base + it.p0 + i, off, best);
         }
-        publish(D.result, B::finish(best));
+        wb.add(B::finish(best));
     }
+    wb.flush();
 }
 
 template <int MP, int KIND>
@@ -47,9 +45,11 @@ __global__ __launch_bounds__(256) void k_bin64(QArgs q)
 {
     using B = Bin64<MP, KIND>;
     const uint32_t lane = threadIdx.x & 63;
+    WaveBest wb;
     Item it;
-    while (pop_item(q, it)) {
+    while (next_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
         int64_t best = B::best_init();
         const uint32_t rounds = (it.count + 63) >> 6;
         for (uint32_t j = 0; j < rounds; ++j) {
@@ -57,8 +57,9 @@ __global__ __launch_bounds__(256) void k_bin64(QArgs q)
             if (i >= it.count) i = it.count - 1;
             B::prefix(D, D.pfx_base + it.p0 + i, best);
         }
-        publish(D.result, B::finish(best));
+        wb.add(B::finish(best));
     }
+    wb.flush();
 }
 
 namespace {

@@ -17,14 +17,11 @@ __global__ __launch_bounds__(256) void k_dary32(QArgs q)
     using K = Dary32<MP, DD, R>;
     const uint32_t lane = threadIdx.x & 63;
     uint32_t off[K::NO][MP];
-    uint32_t loaded = 0xffffffffu;
+    WaveBest wb;
     Item it;
-    while (pop_item(q, it)) {
+    while (next_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
-        if (it.prob != loaded) {
-            K::load_offs(D, off);
-            loaded = it.prob;
-        }
+        if (wb.enter(it.prob, D.result)) K::load_offs(D, off);
         uint32_t best = 0;
         const uint32_t rounds = (it.count + 63) >> 6;
         for (uint32_t j = 0; j < rounds; ++j) {
@@ -32,17 +29,20 @@ __global__ __launch_bounds__(256) void k_dary32(QArgs q)
             if (i >= it.count) i = it.count - 1;
             K::prefix(D, D.pfx_base + it.p0 + i, off, best);
         }
-        publish(D.result, (int64_t)best);
+        wb.add((int64_t)best);
     }
+    wb.flush();
 }
 
 template <int MP, int DD>
 __global__ __launch_bounds__(256) void k_dary64(QArgs q)
 {
     const uint32_t lane = threadIdx.x & 63;
+    WaveBest wb;
     Item it;
-    while (pop_item(q, it)) {
+    while (next_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
         int64_t best = INT64_MIN;
         const uint32_t rounds = (it.count + 63) >> 6;
         for (uint32_t j = 0; j < rounds; ++j) {
@@ -50,8 +50,9 @@ __global__ __launch_bounds__(256) void k_dary64(QArgs q)
             if (i >= it.count) i = it.count - 1;
             Dary64<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, best);
         }
-        publish(D.result, best);
+        wb.add(best);
     }
+    wb.flush();
 }
 
 // Wide sweep (any column count / alphabet), one wave per block; each item's
@@ -60,17 +61,20 @@ __global__ __launch_bounds__(256) void k_dary64(QArgs q)
 __global__ __launch_bounds__(64) void k_wide(QArgs q)
 {
     extern __shared__ int64_t lds[];
+    WaveBest wb;
     Item it;
-    while (pop_item(q, it)) {
+    while (next_item(q, it)) {
         const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
         int64_t best = INT64_MIN;
         for (uint32_t i = 0; i < it.count; ++i) {
             const uint64_t v = D.pfx_base + it.p0 + i;
             if (D.kind == KIND_LD) Wide::prefix_dary(D, v, lds, lds + (size_t)D.d * D.m, best);
             else Wide::prefix_bin(D, v, lds, best);
         }
-        publish(D.result, best);
+        wb.add(best);
     }
+    wb.flush();
 }
 
 // sum_xy |M_xy| of int32 matrices, one block per matrix: the value of L_d when

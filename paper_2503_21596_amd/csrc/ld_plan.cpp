@@ -275,8 +275,17 @@ void choose_binary_shape(Plan& p, const SweepShape& sh, int F)
     if (sh.c_target > 0) {
         C = std::min(Fp, std::max(0, sh.c_target - p.R));
         P = Fp - C;
+        if (sh.pfx_cap > 0 && P > sh.pfx_cap) {
+            P = sh.pfx_cap;
+            C = Fp - P;
+        }
     } else {
-        P = std::min(Fp, sh.p_target);
+        // enough lanes to fill the device, enough words per lane to amortise its
+        // start: 2^c_goal words per prefix, 2^p_min .. 2^p_target prefixes
+        P = F - sh.c_goal;
+        P = std::max(P, std::min(Fp, sh.p_min));
+        P = std::min(P, std::min(Fp, sh.p_target));
+        P = std::max(P, 0);
         C = Fp - P;
         if (C < sh.c_min) {
             C = std::min(Fp, sh.c_min);
@@ -446,6 +455,12 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
         }
     }
     int P = rest - C;
+    // batch planning: a large problem takes more words per prefix, not more prefixes
+    if (sh.pfx_cap > 0)
+        while (P > 0 && rgs_count(p.P_tab, d) * std::pow((double)d, P) > std::ldexp(1.0, sh.pfx_cap)) {
+            --P;
+            ++C;
+        }
     // a single problem should fill the device: trade mid rows for prefix rows
     // (more lanes, fewer words each) while few lanes exist, keeping two mid rows
     if (sh.dary_lanes > 0) {

@@ -11,7 +11,9 @@ namespace ld {
 enum PlanKind : int32_t { PK_L1 = 0, PK_MARG = 1, PK_L2 = 2, PK_LD = 3, PK_SUMABS = 4, PK_ZERO = 5 };
 
 struct SweepShape {
-    int p_target = 20;   // high rows of a large binary problem (2^20 lanes)
+    int p_target = 20;   // at most this many high rows (2^20 lanes) for a binary problem
+    int p_min = 16;      // at least this many, when the problem has them
+    int c_goal = 14;     // between the two: aim for 2^c_goal words per prefix
     int c_min = 4;       // least mid rows per lane when the problem allows it
     int r_drop = 0;      // 1: one low row fewer than the register budget allows
     int dary_ptab = 8;   // restricted-growth prefix rows for d >= 3
@@ -20,6 +22,8 @@ struct SweepShape {
                              // rest of the rows become prefix rows (batch planning)
     int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
+    int pfx_cap = 0;           // > 0 (batch planning): at most about 2^pfx_cap prefixes per
+                               // problem; larger problems get more words per prefix instead
 };
 
 struct Plan {

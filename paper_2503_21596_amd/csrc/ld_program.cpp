@@ -117,7 +117,14 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
             L.lds = p.lds;
             L.implicit = true;
             L.prob = g.second[0];
-            uint64_t per = p.wide ? 1 : sh.lanes_per_item;
+            // items of about item_words words (one lane per prefix), but at least
+            // min_items of them when the problem has that many lane-sized pieces
+            const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);
+            const uint64_t lanes = p.wide ? 1 : sh.lanes_per_item;
+            uint64_t k = 1;
+            if (sh.item_words > 0) k = (uint64_t)std::max(1.0, std::floor(sh.item_words / (wpp * lanes)));
+            const uint64_t kmax = std::max<uint64_t>(1, p.n_prefix / (lanes * std::max<uint32_t>(sh.min_items, 1)));
+            uint64_t per = lanes * std::min(k, kmax);
             per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
             L.per = per;
             L.n_prefix = p.n_prefix;
@@ -128,10 +135,16 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
             continue;
         }
         L.threads = g.first.second != 0 ? 64 : 256;
+        ItemShape gsh = sh;
+        if (sh.max_launch_items > 0 && sh.item_words > 0) {
+            double words = 0;
+            for (uint32_t i : g.second) words += (double)plans[i]->words;
+            gsh.item_words = std::max(sh.item_words, words / sh.max_launch_items);
+        }
         std::vector<std::pair<double, Item>> its;
         for (uint32_t i : g.second) {
             L.lds = std::max(L.lds, plans[i]->lds);
-            split_items(*plans[i], i, sh, its);
+            split_items(*plans[i], i, gsh, its);
         }
         std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         std::vector<Item> items;

@@ -48,7 +48,21 @@ struct ItemShape {
     uint32_t lanes_per_item = 64;   // prefixes per item for the register kernels
     double item_words = 0;          // if > 0: grow items up to about this many words
     uint32_t max_items = 1u << 20;  // per problem
+    uint32_t min_items = 0;         // single problems: keep at least this many items
+    // a launch shared by several problems: grow the items until the launch holds at
+    // most about this many (pops on the one queue head serialize, tens of ns each)
+    uint32_t max_launch_items = 1u << 16;
 };
+
+// queue items of a single-problem launch: about 2^22 words each (pops stay rare
+// next to the work), at least two per resident wave
+inline ItemShape plain_item_shape()
+{
+    ItemShape s;
+    s.item_words = (double)(1u << 22);
+    s.min_items = 4096;
+    return s;
+}
 
 // Split one problem's prefix space into queue items (tagged with problem index
 // `prob`), each with its estimated VALU cost.  `wide` items are swept by one wave

@@ -527,6 +527,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         } else {
             ItemShape sh;
             sh.item_words = S->cfg.words_per_item;
+            sh.max_items = 2048;   // large requests get larger items, not more of them
             std::vector<std::pair<double, Item>> its;
             split_items(r->plan, 0, sh, its);
             std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });

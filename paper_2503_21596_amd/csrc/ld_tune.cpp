@@ -43,7 +43,9 @@ struct Cal {
     std::vector<ld_problem> probs;
 };
 
-// a mixed set shaped like the batch workload, but small enough to time quickly
+// a mixed set with the size law of the batch workload (n in [12, 28], m in
+// [8, 40], d in {1, 2, 3} with n <= 20 for d = 3, a fifth with marginals), fewer
+// problems so that one candidate times in tens of milliseconds
 Cal calibration_batch(int count, uint64_t seed)
 {
     Cal c;
@@ -51,8 +53,9 @@ Cal calibration_batch(int count, uint64_t seed)
     c.mats.resize(count);
     for (int i = 0; i < count; ++i) {
         int d = r.uniform(1, 3);
-        const int marg = (d == 1 && r.uniform(0, 4) == 0) ? 1 : 0;
-        const int n = d == 3 ? r.uniform(10, 15) : r.uniform(12, 22);
+        const int marg = r.uniform(0, 4) == 0 ? 1 : 0;
+        if (marg) d = 1;
+        const int n = d == 3 ? r.uniform(12, 20) : r.uniform(12, 28);
         const int m = r.uniform(8, 40);
         auto& M = c.mats[i];
         M.resize((size_t)n * m);
@@ -97,8 +100,10 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
     if (!f) return false;
     std::fprintf(f,
                  "{\n  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
-                 "  \"plain_p_target\": %d,\n  \"plain_r_drop\": %d,\n  \"measured\": [%s]\n}\n",
-                 t.bin_c_target, t.dary_cwords, t.item_words, t.plain_p_target, t.plain_r_drop, notes.c_str());
+                 "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
+                 "  \"plain_r_drop\": %d,\n  \"measured\": [%s]\n}\n",
+                 t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
+                 t.plain_r_drop, notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -129,6 +134,7 @@ void set_tuning(const Tuning& t)
     }
     SweepShape s = get_shape();
     s.p_target = t.plain_p_target;
+    s.c_goal = t.plain_c_goal;
     s.r_drop = t.plain_r_drop;
     set_shape(s);
 }
@@ -142,6 +148,7 @@ SweepShape batch_shape_for(int n, int m, int d)
     s.c_target = t.bin_c_target;
     s.dary_cwords = t.dary_cwords;
     s.dary_lanes = 0;   // many problems share the device: keep the tuned words per lane
+    s.pfx_cap = t.batch_pfx_cap;
     (void)d;
     return s;
 }
@@ -151,6 +158,7 @@ ItemShape batch_item_shape()
     ItemShape s;
     s.lanes_per_item = 64;
     s.item_words = get_tuning().item_words;
+    s.max_items = 4096;   // per problem: large problems get larger items
     return s;
 }
 
@@ -172,47 +180,50 @@ int ld_autotune(const char* path, double budget_seconds)
     std::string notes;
     char buf[160];
 
-    // batch shape: words per prefix (binary and d-ary) and words per queue item
-    const Cal cal = calibration_batch(384, 0x5eed);
+    // batch shape: words per prefix (binary and d-ary), prefixes per problem and
+    // words per queue item
+    const Cal cal = calibration_batch(256, 0x5eed);
     double best_t = 1e30;
-    const int c_opts[] = {8, 10, 12, 14};
-    const double w_opts[] = {65536.0, 262144.0, 1048576.0};
-    for (int c : c_opts)
-        for (double w : w_opts) {
-            if (now_s() > t_end) break;
-            Tuning t = best;
-            t.bin_c_target = c;
-            t.dary_cwords = c <= 8 ? 729 : c <= 10 ? 2187 : c <= 12 ? 6561 : 19683;
-            t.item_words = w;
-            set_tuning(t);
-            const double dt = time_batch(cal);
-            std::snprintf(buf, sizeof buf, "%s{\"batch_c\": %d, \"item_words\": %.0f, \"ms\": %.3f}",
-                          notes.empty() ? "" : ", ", c, w, 1e3 * dt);
-            notes += buf;
-            if (dt < best_t) {
-                best_t = dt;
-                best = t;
+    for (int c : {8, 10, 12})
+        for (int cap : {10, 12, 14})
+            for (double w : {65536.0, 262144.0}) {
+                if (now_s() > t_end) break;
+                Tuning t = best;
+                t.bin_c_target = c;
+                t.dary_cwords = c <= 8 ? 729 : c <= 10 ? 2187 : 6561;
+                t.batch_pfx_cap = cap;
+                t.item_words = w;
+                set_tuning(t);
+                const double dt = time_batch(cal);
+                std::snprintf(buf, sizeof buf,
+                              "%s{\"batch_c\": %d, \"pfx_cap\": %d, \"item_words\": %.0f, \"ms\": %.3f}",
+                              notes.empty() ? "" : ", ", c, cap, w, 1e3 * dt);
+                notes += buf;
+                if (dt < best_t) {
+                    best_t = dt;
+                    best = t;
+                }
             }
-        }
     set_tuning(best);
 
-    // plain calls: lanes (2^p_target) and low rows, timed on a 30 x 40 L1 problem
+    // plain calls: lane range and words per prefix, timed on a 30 x 40 and a
+    // 35 x 42 L1 problem (sum of the two times)
     {
         Rng r{0xca1};
-        const int n = 30, m = 40;
-        std::vector<int32_t> M((size_t)n * m);
-        for (auto& v : M) v = r.uniform(-100, 100);
+        std::vector<int32_t> A((size_t)30 * 40), B((size_t)35 * 42);
+        for (auto& v : A) v = r.uniform(-100, 100);
+        for (auto& v : B) v = r.uniform(-100, 100);
         double bt = 1e30;
         Tuning bp = best;
-        for (int p : {16, 18, 20, 22})
-            for (int rd : {0, 1}) {
+        for (int p : {18, 20, 22})
+            for (int c : {12, 14, 16}) {
                 if (now_s() > t_end) break;
                 Tuning t = best;
                 t.plain_p_target = p;
-                t.plain_r_drop = rd;
+                t.plain_c_goal = c;
                 set_tuning(t);
-                const double dt = time_plain(M, n, m);
-                std::snprintf(buf, sizeof buf, ", {\"plain_p\": %d, \"r_drop\": %d, \"ms\": %.3f}", p, rd, 1e3 * dt);
+                const double dt = time_plain(A, 30, 40) + time_plain(B, 35, 42);
+                std::snprintf(buf, sizeof buf, ", {\"plain_p\": %d, \"c_goal\": %d, \"ms\": %.3f}", p, c, 1e3 * dt);
                 notes += buf;
                 if (dt < bt) {
                     bt = dt;
@@ -246,7 +257,9 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "bin_c_target", &v)) t.bin_c_target = std::max(0, std::min(40, (int)v));
     if (read_key(text, "dary_cwords", &v)) t.dary_cwords = std::max(1, (int)v);
     if (read_key(text, "item_words", &v)) t.item_words = std::max(1.0, v);
+    if (read_key(text, "batch_pfx_cap", &v)) t.batch_pfx_cap = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_p_target", &v)) t.plain_p_target = std::max(0, std::min(40, (int)v));
+    if (read_key(text, "plain_c_goal", &v)) t.plain_c_goal = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
     set_tuning(t);
     return LD_OK;
