@@ -93,6 +93,18 @@ void ld_batch_release(ld_batch* b);
 int64_t ld_norm_range(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
                       int32_t q, uint64_t prefix_begin, uint64_t prefix_end);
 
+/* ld_argmax -- the value together with one assignment that reaches it (the
+ * strategy the paper's program reports next to the value, Sec. 2.1.3).
+ * assignment (n entries, caller-owned): d = 1: a_x in {-1, +1} for every row
+ * (a_0 = +1 with marginals, Eq. (LMarg)); d >= 2: the message of every row in
+ * {0 .. d-1} (Eq. (L_o_norm)).  col_assignment (m entries, nullable, d = 1 only):
+ * column signs b_y with a^T M b = value (b_0 = +1 with marginals).  Among
+ * several maximisers the one returned is unspecified; it always attains *value.
+ * Cost: the sweep of ld_norm plus one store per prefix and a few small
+ * refinement sweeps.  Returns LD_OK or an error code (as ld_norm's). */
+int ld_argmax(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals, int64_t* value,
+              int32_t* assignment, int32_t* col_assignment);
+
 /* How a problem is laid out for the sweep.  kind: 0 L1, 1 L_marg, 2 L2, 3 L_d
  * (d >= 3), 4 sum|M| (d >= rows), 5 constant zero (empty after preprocessing). */
 typedef struct {
@@ -187,11 +199,14 @@ int ld_plan(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals
 uint32_t ld_gray_digit(uint32_t d, uint32_t i, uint64_t j);
 int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
 
-/* Sweep shape used for new plans (0 = keep).  p_target: high rows (lanes =
- * 2^p_target) for large binary problems; c_min: least mid rows per lane;
- * r_drop: 1 to score one low row fewer per state than the register budget allows;
- * dary_ptab: rows covered by restricted-growth prefixes (<= 16). */
-void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab);
+/* Sweep shape used for new plans (0 = keep, and -1 = keep for r_drop and sgpr_r).
+ * p_target: high rows (lanes = 2^p_target) for large binary problems; c_min: least
+ * mid rows per lane; r_drop: 1 to score one low row fewer per state than the
+ * register budget of the VGPR-operand kernel allows; dary_ptab: rows covered by
+ * restricted-growth prefixes (<= 16); sgpr_r: low rows scored per state by the
+ * int32 binary kernel that reads its low-row operands from SGPRs (4 or 5), or 0
+ * for the kernel that holds them in VGPRs.  Values never depend on the shape. */
+void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r);
 
 /* Autotuner.  The paper found no general rule for the launch shape and advises
  * timing a smaller matrix first (Sec. 4).  ld_autotune times candidate shapes on

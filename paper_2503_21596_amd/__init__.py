@@ -61,12 +61,13 @@ SIGNATURES = {
     "ld_norm": (_I64, [_P, _I32, _I32, _I32, _I32]),
     "ld_norm_batch": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "ld_norm_range": (_I64, [_P, _I32, _I32, _I32, _I32, _I32, _U64, _U64]),
+    "ld_argmax": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _P]),
     "ld_last_error": (ctypes.c_int, []),
     "ld_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ld_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
     "ld_gray_digit": (_U32, [_U32, _U32, _U64]),
     "ld_gray_change": (_I32, [_U32, _U64, _P, _P]),
-    "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32]),
+    "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32, _I32]),
     "ld_prepare": (_P, [_P, _I32, _I32, _I32, _I32]),
     "ld_run": (ctypes.c_int, [_P, _P, _P]),
     "ld_last_kernel_ms": (ctypes.c_float, [_P]),
@@ -144,6 +145,22 @@ def ld_norm_range(M, d: int, marginals: int, q: int, prefix_begin: int, prefix_e
     if v == INT64_MIN:
         raise _err()
     return int(v)
+
+
+def ld_argmax(M, d: int = 1, marginals: int = 0):
+    """(value, a, b): the value and one assignment reaching it.  a holds one entry
+    per row (signs for d = 1, messages for d >= 2); b the column signs for d = 1
+    (None for d >= 2)."""
+    a = _mat(M)
+    n, m = a.shape
+    v = np.zeros(1, dtype=np.int64)
+    rows = np.zeros(n, dtype=np.int32)
+    cols = np.zeros(m, dtype=np.int32)
+    rc = lib().ld_argmax(a.ctypes.data, n, m, int(d), int(marginals), v.ctypes.data, rows.ctypes.data,
+                         cols.ctypes.data if d == 1 else None)
+    if rc != LD_OK:
+        raise _err(rc)
+    return int(v[0]), rows, (cols if d == 1 else None)
 
 
 def ld_norm_batch(problems: Sequence[Tuple], stream=None, return_status: bool = False):
@@ -262,8 +279,9 @@ def gray_change(d: int, j: int):
     return int(i), int(f.value), int(t.value)
 
 
-def set_sweep_shape(p_target: int = 0, c_min: int = 0, r_drop: int = -1, dary_ptab: int = 0) -> None:
-    lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab)
+def set_sweep_shape(p_target: int = 0, c_min: int = 0, r_drop: int = -1, dary_ptab: int = 0,
+                    sgpr_r: int = -1) -> None:
+    lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab, sgpr_r)
 
 
 def autotune(path: Optional[str] = None, budget_seconds: float = 20.0) -> None:

@@ -30,6 +30,7 @@ UNITS = [
     ("ld_batch.cpp", [], "batch.o"),
     ("ld_server.cpp", [], "server.o"),
     ("ld_tune.cpp", [], "tune.o"),
+    ("ld_argmax.cpp", [], "argmax.o"),
 ]
 
 

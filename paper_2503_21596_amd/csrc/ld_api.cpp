@@ -306,13 +306,14 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to)
     return (int32_t)i;
 }
 
-void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab)
+void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r)
 {
     SweepShape s = get_shape();
     if (p_target > 0) s.p_target = std::min(p_target, 40);
     if (c_min > 0) s.c_min = std::min(c_min, 31);
     if (r_drop >= 0) s.r_drop = r_drop ? 1 : 0;
     if (dary_ptab > 0) s.dary_ptab = std::min(dary_ptab, 16);
+    if (sgpr_r >= 0) s.sgpr_r = std::min(sgpr_r, MAX_RS);
     set_shape(s);
 }
 

@@ -33,7 +33,36 @@ __global__ __launch_bounds__(256) void k_bin32(QArgs q)
         for (uint32_t j = 0; j < rounds; ++j) {
             uint32_t i = lane + 64 * j;
             if (i >= it.count) i = it.count - 1;
-            B::prefix(D, D.pfx_base + it.p0 + i, off, best);
+            uint32_t pb = B::best_init();
+            B::prefix(D, D.pfx_base + it.p0 + i, off, pb);
+            best = B::better(best, pb);
+            if (D.rec) D.rec[it.p0 + i] = B::finish(pb);
+        }
+        wb.add(B::finish(best));
+    }
+    wb.flush();
+}
+
+// Same queue loop with the low-row operands streamed through SGPRs (Bin32S).
+template <int MP, int KIND, int R>
+__global__ __launch_bounds__(256) void k_bin32s(QArgs q)
+{
+    using B = Bin32S<MP, KIND, R>;
+    const uint32_t lane = threadIdx.x & 63;
+    WaveBest wb;
+    Item it;
+    while (next_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
+        uint32_t best = B::best_init();
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            uint32_t pb = B::best_init();
+            B::prefix(D, D.pfx_base + it.p0 + i, pb);
+            best = B::better(best, pb);
+            if (D.rec) D.rec[it.p0 + i] = B::finish(pb);
         }
         wb.add(B::finish(best));
     }
@@ -55,7 +84,10 @@ __global__ __launch_bounds__(256) void k_bin64(QArgs q)
         for (uint32_t j = 0; j < rounds; ++j) {
             uint32_t i = lane + 64 * j;
             if (i >= it.count) i = it.count - 1;
-            B::prefix(D, D.pfx_base + it.p0 + i, best);
+            int64_t pb = B::best_init();
+            B::prefix(D, D.pfx_base + it.p0 + i, pb);
+            best = pb > best ? pb : best;
+            if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(B::finish(best));
     }
@@ -66,6 +98,7 @@ namespace {
 
 constexpr int NMP = MAX_MP / 2;   // mp = 2, 4, ..., 64
 const void* g_bin32[NMP][MAX_R + 1] = {};
+const void* g_bin32s[NMP][MAX_RS + 1] = {};
 const void* g_bin64[MAX_MP / 8] = {};
 
 template <int MP, int R>
@@ -82,6 +115,8 @@ void reg_mp()
     reg_one<MP, rmax>();
     if constexpr (rmax >= 1) reg_one<MP, rmax - 1>();
     if constexpr (MP % 8 == 0) g_bin64[MP / 8 - 1] = (const void*)&k_bin64<MP, LD_KIND>;
+    g_bin32s[MP / 2 - 1][4] = (const void*)&k_bin32s<MP, LD_KIND, 4>;
+    g_bin32s[MP / 2 - 1][5] = (const void*)&k_bin32s<MP, LD_KIND, 5>;
 }
 
 template <int... I>
@@ -103,6 +138,12 @@ const void* LD_CAT(lookup_bin32_kind, LD_KIND)(int mp, int R)
 {
     if (mp < 2 || mp > MAX_MP || (mp & 1) || R < 0 || R > MAX_R) return nullptr;
     return g_bin32[mp / 2 - 1][R];
+}
+
+const void* LD_CAT(lookup_bin32s_kind, LD_KIND)(int mp, int R)
+{
+    if (mp < 2 || mp > MAX_MP || (mp & 1) || R < 0 || R > MAX_RS) return nullptr;
+    return g_bin32s[mp / 2 - 1][R];
 }
 
 const void* LD_CAT(lookup_bin64_kind, LD_KIND)(int mp)

@@ -27,7 +27,10 @@ __global__ __launch_bounds__(256) void k_dary32(QArgs q)
         for (uint32_t j = 0; j < rounds; ++j) {
             uint32_t i = lane + 64 * j;
             if (i >= it.count) i = it.count - 1;
-            K::prefix(D, D.pfx_base + it.p0 + i, off, best);
+            uint32_t pb = 0;
+            K::prefix(D, D.pfx_base + it.p0 + i, off, pb);
+            best = max(best, pb);
+            if (D.rec) D.rec[it.p0 + i] = (int64_t)pb;
         }
         wb.add((int64_t)best);
     }
@@ -48,7 +51,10 @@ __global__ __launch_bounds__(256) void k_dary64(QArgs q)
         for (uint32_t j = 0; j < rounds; ++j) {
             uint32_t i = lane + 64 * j;
             if (i >= it.count) i = it.count - 1;
-            Dary64<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, best);
+            int64_t pb = INT64_MIN;
+            Dary64<MP, DD>::prefix(D, D.pfx_base + it.p0 + i, pb);
+            best = pb > best ? pb : best;
+            if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(best);
     }
@@ -69,8 +75,11 @@ __global__ __launch_bounds__(64) void k_wide(QArgs q)
         int64_t best = INT64_MIN;
         for (uint32_t i = 0; i < it.count; ++i) {
             const uint64_t v = D.pfx_base + it.p0 + i;
-            if (D.kind == KIND_LD) Wide::prefix_dary(D, v, lds, lds + (size_t)D.d * D.m, best);
-            else Wide::prefix_bin(D, v, lds, best);
+            int64_t pb = INT64_MIN;
+            if (D.kind == KIND_LD) Wide::prefix_dary(D, v, lds, lds + (size_t)D.d * D.m, pb);
+            else Wide::prefix_bin(D, v, lds, pb);
+            best = pb > best ? pb : best;
+            if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(best);
     }
@@ -134,6 +143,40 @@ __global__ __launch_bounds__(256) void k_reset_slots(int64_t* __restrict__ resul
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
 }
 
+// Locating a maximiser: *first = the smallest i < n with rec[i] == target (the
+// caller sets *first to UINT64_MAX beforehand with k_set_u64).
+__global__ __launch_bounds__(256) void k_first_equal(const int64_t* __restrict__ rec, uint64_t n, int64_t target,
+                                                     unsigned long long* __restrict__ first)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (rec[i] == target) atomicMin(first, (unsigned long long)i);
+}
+
+__global__ __launch_bounds__(64) void k_set_u64(unsigned long long* __restrict__ p, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// The other side of a binary strategy (Eq. LM2 is a max over a and b of a^T M b):
+// out[i] = sign(sum_j A[i][j] v[j]) with ties to +1, for A = M (rows = 1) or M^T
+// (rows = 0), M int32 n x m row-major, v in {-1, +1}.  fix0: out[0] = +1 (the
+// marginal row or column of Eq. LMarg).
+__global__ __launch_bounds__(256) void k_signs(const int32_t* __restrict__ M, int32_t n, int32_t m,
+                                               const int32_t* __restrict__ v, int32_t rows, int32_t fix0,
+                                               int32_t* __restrict__ out)
+{
+    const int32_t len = rows ? n : m, other = rows ? m : n;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+        int64_t acc = 0;
+        for (int32_t j = 0; j < other; ++j) {
+            const int64_t e = rows ? M[(size_t)i * m + j] : M[(size_t)j * m + i];
+            acc += e * v[j];
+        }
+        out[i] = (fix0 && i == 0) ? 1 : (acc < 0 ? -1 : 1);
+    }
+}
+
 namespace {
 
 constexpr int NMPD = MAX_MP / 4;   // mp = 4, 8, ..., 64
@@ -187,10 +230,16 @@ const void* kernel_wide() { return (const void*)&k_wide; }
 const void* kernel_reset() { return (const void*)&k_reset; }
 const void* kernel_scatter() { return (const void*)&k_scatter; }
 const void* kernel_reset_slots() { return (const void*)&k_reset_slots; }
+const void* kernel_first_equal() { return (const void*)&k_first_equal; }
+const void* kernel_set_u64() { return (const void*)&k_set_u64; }
+const void* kernel_signs() { return (const void*)&k_signs; }
 
 const void* lookup_bin32_kind0(int mp, int R);
 const void* lookup_bin32_kind1(int mp, int R);
 const void* lookup_bin32_kind2(int mp, int R);
+const void* lookup_bin32s_kind0(int mp, int R);
+const void* lookup_bin32s_kind1(int mp, int R);
+const void* lookup_bin32s_kind2(int mp, int R);
 const void* lookup_bin64_kind0(int mp);
 const void* lookup_bin64_kind1(int mp);
 const void* lookup_bin64_kind2(int mp);
@@ -201,6 +250,16 @@ const void* kernel_bin32(int kind, int mp, int R)
     case KIND_L1: return lookup_bin32_kind0(mp, R);
     case KIND_MARG: return lookup_bin32_kind1(mp, R);
     case KIND_L2: return lookup_bin32_kind2(mp, R);
+    default: return nullptr;
+    }
+}
+
+const void* kernel_bin32s(int kind, int mp, int R)
+{
+    switch (kind) {
+    case KIND_L1: return lookup_bin32s_kind0(mp, R);
+    case KIND_MARG: return lookup_bin32s_kind1(mp, R);
+    case KIND_L2: return lookup_bin32s_kind2(mp, R);
     default: return nullptr;
     }
 }

@@ -19,6 +19,9 @@ SweepShape g_shape;
 struct Mat {
     int n = 0, m = 0;
     std::vector<int32_t> a;
+    // input rows / columns folded into each row / column, with the sign they enter with
+    // (preprocessing only; a merge appends the members of the row it absorbs)
+    std::vector<Members> ri, ci;
     int32_t at(int x, int y) const { return a[(size_t)x * m + y]; }
 };
 
@@ -30,6 +33,8 @@ Mat transpose(const Mat& A)
     T.a.resize(A.a.size());
     for (int x = 0; x < A.n; ++x)
         for (int y = 0; y < A.m; ++y) T.a[(size_t)y * T.m + x] = A.at(x, y);
+    T.ri = A.ci;
+    T.ci = A.ri;
     return T;
 }
 
@@ -62,6 +67,8 @@ Mat drop_zeros(const Mat& A, bool keep0)
     B.a.resize((size_t)B.n * B.m);
     for (int i = 0; i < B.n; ++i)
         for (int j = 0; j < B.m; ++j) B.a[(size_t)i * B.m + j] = A.at(rows[i], cols[j]);
+    for (int x : rows) B.ri.push_back(A.ri[x]);
+    for (int y : cols) B.ci.push_back(A.ci[y]);
     return B;
 }
 
@@ -73,7 +80,135 @@ Mat drop_first_row_col(const Mat& A)
     B.a.resize((size_t)std::max(0, B.n) * std::max(0, B.m));
     for (int x = 1; x < A.n; ++x)
         for (int y = 1; y < A.m; ++y) B.a[(size_t)(x - 1) * B.m + (y - 1)] = A.at(x, y);
+    B.ri.assign(A.ri.begin() + std::min<size_t>(1, A.ri.size()), A.ri.end());
+    B.ci.assign(A.ci.begin() + std::min<size_t>(1, A.ci.size()), A.ci.end());
     return B;
+}
+
+// --- exact reductions (Sec. 2.1.1, Sec. 2.2, Sec. 2.3.1; Appendices A and B) ---
+
+// v = c u for some c != 0 (both rows nonzero): returns sign(c), else 0
+int proportional(const int32_t* u, const int32_t* v, int len, int stride)
+{
+    int k = 0;
+    while (k < len && u[(size_t)k * stride] == 0) ++k;
+    if (k == len || v[(size_t)k * stride] == 0) return 0;
+    const int64_t uk = u[(size_t)k * stride], vk = v[(size_t)k * stride];
+    for (int y = 0; y < len; ++y)
+        if ((int64_t)v[(size_t)y * stride] * uk != (int64_t)u[(size_t)y * stride] * vk) return 0;
+    return ((uk < 0) == (vk < 0)) ? 1 : -1;
+}
+
+bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
+
+// Merge proportional rows (rows = true) or columns: the pair is replaced by the
+// first plus sign(c) times the second, i.e. (1 + |c|) times the first.  A merge
+// needs `allow(sign)` (rule A1: any sign for d = 1; A2: any sign for columns when
+// d >= 2; A3: c > 0 only for rows when d >= 2); index 0 is left alone when keep0
+// (the marginal row / column of Eq. LMarg).  Merges that would overflow int32 are
+// skipped.  Returns true if anything merged.
+template <class Allow>
+bool merge_proportional(Mat& A, bool rows, bool keep0, Allow allow)
+{
+    const int cnt = rows ? A.n : A.m, len = rows ? A.m : A.n;
+    const int stride = rows ? 1 : A.m;   // step between the entries of one row / column
+    auto line = [&](int i) { return A.a.data() + (rows ? (size_t)i * A.m : (size_t)i); };
+    std::vector<char> gone(cnt, 0);
+    bool any = false;
+    for (int i = keep0 ? 1 : 0; i < cnt; ++i) {
+        if (gone[i]) continue;
+        for (int j = i + 1; j < cnt; ++j) {
+            if (gone[j]) continue;
+            const int sg = proportional(line(i), line(j), len, stride);
+            if (sg == 0 || !allow(sg)) continue;
+            bool ok = true;
+            for (int t = 0; t < len && ok; ++t)
+                ok = fits_i32((int64_t)line(i)[(size_t)t * stride] + sg * (int64_t)line(j)[(size_t)t * stride]);
+            if (!ok) continue;
+            for (int t = 0; t < len; ++t) line(i)[(size_t)t * stride] += sg * line(j)[(size_t)t * stride];
+            auto& to = rows ? A.ri[i] : A.ci[i];
+            for (auto mb : (rows ? A.ri[j] : A.ci[j])) to.push_back({mb.first, mb.second * sg});
+            gone[j] = 1;
+            any = true;
+        }
+    }
+    if (!any) return false;
+    // compact: drop the absorbed rows / columns
+    std::vector<int> keep;
+    for (int i = 0; i < cnt; ++i)
+        if (!gone[i]) keep.push_back(i);
+    Mat B;
+    B.n = rows ? (int)keep.size() : A.n;
+    B.m = rows ? A.m : (int)keep.size();
+    B.a.resize((size_t)B.n * B.m);
+    for (int x = 0; x < B.n; ++x)
+        for (int y = 0; y < B.m; ++y) B.a[(size_t)x * B.m + y] = rows ? A.at(keep[x], y) : A.at(x, keep[y]);
+    B.ri = A.ri;
+    B.ci = A.ci;
+    if (rows) {
+        B.ri.clear();
+        for (int i : keep) B.ri.push_back(A.ri[i]);
+    } else {
+        B.ci.clear();
+        for (int i : keep) B.ci.push_back(A.ci[i]);
+    }
+    A = std::move(B);
+    return true;
+}
+
+// d >= 2 (Appendix A): columns whose entries all share one sign (zeros allowed)
+// merge into one column of |M_xy1| + |M_xy2| + ...  Skipped on int32 overflow.
+bool merge_uniform_columns(Mat& A)
+{
+    std::vector<int> uni;
+    for (int y = 0; y < A.m; ++y) {
+        bool pos = true, neg = true;
+        for (int x = 0; x < A.n; ++x) {
+            pos = pos && A.at(x, y) >= 0;
+            neg = neg && A.at(x, y) <= 0;
+        }
+        if (pos || neg) uni.push_back(y);
+    }
+    if (uni.size() < 2) return false;
+    std::vector<int64_t> col(A.n, 0);
+    for (int x = 0; x < A.n; ++x) {
+        for (int y : uni) col[x] += std::abs((int64_t)A.at(x, y));
+        if (!fits_i32(col[x])) return false;
+    }
+    const int y0 = uni[0];
+    for (int x = 0; x < A.n; ++x) A.a[(size_t)x * A.m + y0] = (int32_t)col[x];
+    for (size_t k = 1; k < uni.size(); ++k)
+        for (auto mb : A.ci[uni[k]]) A.ci[y0].push_back(mb);
+    std::vector<int> keep;
+    for (int y = 0; y < A.m; ++y)
+        if (y == y0 || std::find(uni.begin(), uni.end(), y) == uni.end()) keep.push_back(y);
+    Mat B;
+    B.n = A.n;
+    B.m = (int)keep.size();
+    B.a.resize((size_t)B.n * B.m);
+    for (int x = 0; x < B.n; ++x)
+        for (int j = 0; j < B.m; ++j) B.a[(size_t)x * B.m + j] = A.at(x, keep[j]);
+    B.ri = A.ri;
+    for (int y : keep) B.ci.push_back(A.ci[y]);
+    A = std::move(B);
+    return true;
+}
+
+// All merges for one kind, repeated until none applies.
+void reduce(Mat& A, int d, bool marg)
+{
+    for (bool again = true; again;) {
+        again = false;
+        if (d == 1) {
+            auto any = [](int) { return true; };
+            again |= merge_proportional(A, true, marg, any);
+            again |= merge_proportional(A, false, marg, any);
+        } else {
+            again |= merge_proportional(A, true, false, [](int sg) { return sg > 0; });
+            again |= merge_proportional(A, false, false, [](int) { return true; });
+            again |= merge_uniform_columns(A);
+        }
+    }
 }
 
 int64_t sum_abs(const Mat& A)
@@ -125,7 +260,7 @@ void build_binary(Plan& p, const Mat& A)
         p.off_hid = align256(p.off_base + 4 * (size_t)mp);
         p.off_mid = align256(p.off_hid + 4 * (size_t)std::max(P, 1) * RS);
         p.off_offs = align256(p.off_mid + 4 * (size_t)std::max(C, 1) * 2 * RS);
-        p.off_tab = align256(p.off_offs + 4 * (size_t)K * NW * mp);
+        p.off_tab = align256(p.off_offs + 4 * (size_t)K * NW * RS);
         p.blob.assign(p.off_tab, 0);
         for (int y = 0; y < mp; ++y) put<uint32_t>(p.blob, p.off_base, y, (uint32_t)(base[y] + BIAS));
         for (int h = 0; h < P; ++h)
@@ -144,9 +279,9 @@ void build_binary(Plan& p, const Mat& A)
                     for (int i = 0; i < R; ++i) low += ((w >> i) & 1) ? v1(1 + i, y) : v0(1 + i, y);
                 // |s - o| with s = true + 2^31 must equal |true + low| (and for L2
                 // the second operand gives |total - (true + low)|)
-                put<uint32_t>(p.blob, p.off_offs, (size_t)w * mp + y, (uint32_t)(BIAS - low));
+                put<uint32_t>(p.blob, p.off_offs, (size_t)w * RS + y, (uint32_t)(BIAS - low));
                 if (l2)
-                    put<uint32_t>(p.blob, p.off_offs, (size_t)(NW + w) * mp + y,
+                    put<uint32_t>(p.blob, p.off_offs, (size_t)(NW + w) * RS + y,
                                   (uint32_t)(BIAS + total[y] - low));
             }
     } else {
@@ -312,6 +447,20 @@ bool use_wide(Plan& p, int states)
     return p.lds <= WIDE_LDS_MAX;
 }
 
+// int32 binary kernel: the SGPR-operand kernel with sh.sgpr_r low rows when it
+// exists for this width, else the VGPR-operand kernel with as many low rows as
+// its register budget allows
+void pick_bin32(Plan& p, const SweepShape& sh)
+{
+    p.kernel = sh.sgpr_r > 0 ? kernel_bin32s(p.kind, p.mp, sh.sgpr_r) : nullptr;
+    if (p.kernel) {
+        p.R = sh.sgpr_r;
+        return;
+    }
+    p.R = std::max(0, bin_rmax(p.mp, p.kind) - (sh.r_drop ? 1 : 0));
+    p.kernel = kernel_bin32(p.kind, p.mp, p.R);
+}
+
 Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
 {
     // A: row 0 fixed; p.kind set; p.i64 set
@@ -324,11 +473,10 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
     if (A.m <= MAX_MP && p.mp <= MAX_MP) {
         if (p.i64) {
             p.R = 0;
+            p.kernel = kernel_bin64(p.kind, p.mp);
         } else {
-            const int rmax = bin_rmax(p.mp, p.kind);
-            p.R = std::max(0, rmax - (sh.r_drop ? 1 : 0));
+            pick_bin32(p, sh);
         }
-        p.kernel = p.i64 ? kernel_bin64(p.kind, p.mp) : kernel_bin32(p.kind, p.mp, p.R);
     }
     if (!p.kernel) {
         p.R = 0;
@@ -382,6 +530,8 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     A.n = n;
     A.m = m;
     A.a.assign(M, M + (size_t)n * m);
+    for (int x = 0; x < n; ++x) A.ri.push_back({{x, 1}});
+    for (int y = 0; y < m; ++y) A.ci.push_back({{y, 1}});
     p.d = d;
 
     if (d == 1 && marginals) {
@@ -398,6 +548,7 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
         A = drop_zeros(A, false);
         p.kind = d == 1 ? PK_L1 : (d == 2 ? PK_L2 : PK_LD);
     }
+    if (sh.merge && A.n > 0 && A.m > 0) reduce(A, d, p.kind == PK_MARG);
     if (A.n == 0 || A.m == 0) {
         p.kind = PK_ZERO;
         p.n = p.m = 0;
@@ -415,6 +566,8 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     p.n = A.n;
     p.m = A.m;
     p.d = std::min(d, A.n);
+    p.row_members = A.ri;
+    p.col_members = A.ci;
     const int64_t B = sum_abs(A);
     p.i64 = B > (int64_t)0x7fffffff ? 1 : 0;
 
@@ -528,10 +681,14 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
 
     if (p.kind != PK_LD) {
         p.mp = p.i64 ? pad_bin64(m) : pad_bin32(m);
-        p.R = p.i64 ? 0 : bin_rmax(p.mp, p.kind);
+        p.R = 0;
         p.kernel = nullptr;
-        if (m <= MAX_MP && p.mp <= MAX_MP)
-            p.kernel = p.i64 ? kernel_bin64(p.kind, p.mp) : kernel_bin32(p.kind, p.mp, p.R);
+        if (m <= MAX_MP && p.mp <= MAX_MP) {
+            if (p.i64)
+                p.kernel = kernel_bin64(p.kind, p.mp);
+            else
+                pick_bin32(p, get_shape());
+        }
         if (!p.kernel) {
             p.R = 0;
             if (!use_wide(p, 1)) {

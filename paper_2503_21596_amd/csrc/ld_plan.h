@@ -2,6 +2,7 @@
 // sweep and the device tables of one problem.
 #pragma once
 #include <stdint.h>
+#include <utility>
 #include <vector>
 
 #include "ld_types.h"
@@ -9,6 +10,9 @@
 namespace ld {
 
 enum PlanKind : int32_t { PK_L1 = 0, PK_MARG = 1, PK_L2 = 2, PK_LD = 3, PK_SUMABS = 4, PK_ZERO = 5 };
+
+// (input index, sign) pairs folded into one row or column by preprocessing
+using Members = std::vector<std::pair<int, int>>;
 
 struct SweepShape {
     int p_target = 20;   // at most this many high rows (2^20 lanes) for a binary problem
@@ -22,6 +26,10 @@ struct SweepShape {
                              // rest of the rows become prefix rows (batch planning)
     int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
+    int sgpr_r = 4;            // int32 binary kinds: low rows of the SGPR-operand kernel
+                               // (4 or 5); 0 selects the VGPR-operand kernel
+    int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
+                               // sign columns before planning (exact reductions)
     int pfx_cap = 0;           // > 0 (batch planning): at most about 2^pfx_cap prefixes per
                                // problem; larger problems get more words per prefix instead
 };
@@ -39,10 +47,14 @@ struct Plan {
     uint64_t dpow_free = 1;
     double words = 0;
     std::vector<int32_t> M;    // preprocessed matrix, n x m
+    // per row / column of M: the input rows / columns (input columns / rows when
+    // transposed) folded into it by preprocessing, each with the sign it enters with
+    std::vector<Members> row_members, col_members;
     // device tables, laid out in one blob; offsets in bytes, each 256-aligned
     std::vector<uint8_t> blob;
     size_t off_base = 0, off_hid = 0, off_mid = 0, off_offs = 0, off_tab = 0;
     const void* kernel = nullptr;  // sweep kernel, null for PK_ZERO / PK_SUMABS
+    int record = 0;                // 1: the sweep also stores every prefix's maximum
     int wide = 0;                  // 1: the wide (LDS-state, one wave per prefix) kernel
     size_t lds = 0;                // dynamic LDS bytes of the wide kernel
 };

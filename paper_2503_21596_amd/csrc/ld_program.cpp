@@ -175,6 +175,12 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
     P.n_sums = (uint32_t)sums.size();
     P.off_sums = off;
     off = align256(off + sizeof(SumItem) * (size_t)std::max<uint32_t>(P.n_sums, 1));
+    P.rec_off.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i)
+        if (plans[i]->record && plans[i]->kernel && plans[i]->kind != PK_ZERO) {
+            P.rec_off[i] = off;
+            off = align256(off + 8 * (size_t)plans[i]->n_prefix);
+        }
 
     P.image.assign(off, 0);
     Rel rel;
@@ -202,6 +208,7 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
         D.offs = (const void*)(uintptr_t)(P.blob_off[i] + p.off_offs);
         D.tab = (const uint64_t*)(uintptr_t)(P.blob_off[i] + p.off_tab);
         D.result = (int64_t*)(uintptr_t)(P.off_results + 8 * (size_t)i);
+        D.rec = (int64_t*)(uintptr_t)P.rec_off[i];
         rel.descs[i] = D;
     }
     for (auto& l : launches) {
@@ -244,6 +251,7 @@ void patch_program(Program& P, void* dev)
             fix(D.offs);
             fix(D.tab);
             fix(D.result);
+            if (D.rec) fix(D.rec);
         }
         std::memcpy(P.image.data() + P.off_descs + i * sizeof(Desc), &D, sizeof(Desc));
     }

@@ -39,6 +39,8 @@ struct Program {
     size_t off_descs = 0, off_items = 0, off_heads = 0, off_results = 0, off_sums = 0;
     uint32_t n_probs = 0, n_heads = 0, n_sums = 0;
     std::vector<size_t> blob_off;            // per problem, byte offset of its tables
+    std::vector<size_t> rec_off;             // per problem, byte offset of its per-prefix
+                                             // maxima (0: not recorded, see Plan::record)
     std::vector<Launch> launches;
     std::vector<int> zero;                   // problems whose value is 0 without a search
     void* dev = nullptr;                     // device address the image was patched for

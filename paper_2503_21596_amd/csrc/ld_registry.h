@@ -14,6 +14,7 @@ namespace ld {
 // SIMD (512 VGPRs per lane slot) with room for temporaries.
 constexpr int VGPR_STATE_BUDGET = 224;
 constexpr int MAX_R = 3;
+constexpr int MAX_RS = 5;   // low rows of the SGPR-operand binary kernels (R = 4, 5 built)
 
 constexpr int bin_k(int kind) { return kind == 2 ? 2 : 1; }
 
@@ -43,6 +44,7 @@ struct KernelRef {
 
 // lookups; return nullptr when no instantiation exists
 const void* kernel_bin32(int kind, int mp, int R);
+const void* kernel_bin32s(int kind, int mp, int R);
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
 const void* kernel_dary64(int d, int mp);
@@ -51,6 +53,9 @@ const void* kernel_wide();
 const void* kernel_reset();
 const void* kernel_scatter();
 const void* kernel_reset_slots();
+const void* kernel_first_equal();
+const void* kernel_set_u64();
+const void* kernel_signs();
 constexpr size_t WIDE_LDS_MAX = 64 * 1024;   // bytes of state per wave
 
 // padded column count used for a problem with m columns

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "ld_gray.h"
 #include "ld_types.h"
 
@@ -50,6 +52,68 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x)
     return r;
 }
 
+// v_sad_u32 with the operand b taken from an SGPR
+__device__ __forceinline__ uint32_t sad_u32_s(uint32_t a, uint32_t b, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(acc));
+    return r;
+}
+
+// Compile-time loop: f(integral_constant<int, i>) for i = 0 .. N-1, so that
+// offsets derived from i can be immediates of a load.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+// Four 8-dword scalar loads at base + O0 .. O3 (wave-uniform base in SGPRs),
+// complete on return.  Scalar loads may return out of order, so one wait for all
+// of them closes the statement; keeping the wait inside the statement means no
+// instruction can touch the destination SGPRs while a load is still in flight.
+// The destinations are early-clobber ("=&s"): a later load of the statement still
+// reads `base`, so no destination may share its registers (a first load landing
+// on the base pair would redirect the ones after it).
+template <int O0, int O1, int O2, int O3>
+__device__ __forceinline__ void sload_4x8(uint64_t base, u32x8& x0, u32x8& x1, u32x8& x2, u32x8& x3)
+{
+    asm volatile("s_load_dwordx8 %0, %4, %5\n\t"
+                 "s_load_dwordx8 %1, %4, %6\n\t"
+                 "s_load_dwordx8 %2, %4, %7\n\t"
+                 "s_load_dwordx8 %3, %4, %8\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(x0), "=&s"(x1), "=&s"(x2), "=&s"(x3)
+                 : "s"(base), "n"(O0), "n"(O1), "n"(O2), "n"(O3));
+}
+
+template <int O0, int O1>
+__device__ __forceinline__ void sload_2x8(uint64_t base, u32x8& x0, u32x8& x1)
+{
+    asm volatile("s_load_dwordx8 %0, %2, %3\n\t"
+                 "s_load_dwordx8 %1, %2, %4\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(x0), "=&s"(x1)
+                 : "s"(base), "n"(O0), "n"(O1));
+}
+
+template <int O0>
+__device__ __forceinline__ void sload_1x8(uint64_t base, u32x8& x0)
+{
+    asm volatile("s_load_dwordx8 %0, %1, %2\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&s"(x0)
+                 : "s"(base), "n"(O0));
+}
+
 // ---------------------------------------------------------------------------
 // binary kinds, int32 (offset-binary) path
 
@@ -64,6 +128,12 @@ struct Bin32 {
     // best starts at the smallest score of its kind (0, or INT32_MIN for L_marg)
     __device__ static constexpr uint32_t best_init() { return KIND == KIND_MARG ? 0x80000000u : 0u; }
 
+    __device__ static __forceinline__ uint32_t better(uint32_t a, uint32_t b)
+    {
+        if constexpr (KIND == KIND_MARG) return (uint32_t)max((int32_t)a, (int32_t)b);
+        else return max(a, b);
+    }
+
     __device__ static __forceinline__ void load_offs(const Desc& D, uint32_t (&off)[K][NW][MP])
     {
         cptr<uint32_t> o = as_const<uint32_t>(D.offs);
@@ -72,7 +142,7 @@ struct Bin32 {
 #pragma unroll
             for (int w = 0; w < NW; ++w)
 #pragma unroll
-                for (int y = 0; y < MP; ++y) off[k][w][y] = in_vgpr(o[(k * NW + w) * MP + y]);
+                for (int y = 0; y < MP; ++y) off[k][w][y] = in_vgpr(o[(k * NW + w) * RS + y]);
     }
 
     __device__ static __forceinline__ void score(const uint32_t (&s)[MP], const uint32_t (&off)[K][NW][MP],
@@ -135,6 +205,142 @@ struct Bin32 {
             score(s, off, best);
 #pragma unroll
             for (int y = 0; y < MP; ++y) s[y] += (uint32_t)nx[y];
+        }
+    }
+
+    __device__ static __forceinline__ int64_t finish(uint32_t best)
+    {
+        if constexpr (KIND == KIND_MARG) return (int64_t)(int32_t)best;
+        else return (int64_t)best;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// binary kinds, int32 path, low-row operands streamed through SGPRs
+//
+// The low-row operands are the same in every lane, so instead of holding copies
+// in VGPRs (which caps R at 2 for m = 42) they are read with scalar loads straight
+// into SGPRs and consumed as the scalar operand of v_sad_u32.  Only the state vector
+// lives in VGPRs, so R is free: a state is scored for 2^R words and its row update
+// costs 1/2^R of the scoring.  The small register footprint also allows seven
+// waves per SIMD, which hides the scalar-load latency.
+//
+// Operand streams are consumed four at a time (four independent accumulators) so
+// that dependent v_sad_u32 instructions are four apart.  Stream order: for L1 and
+// L_marg stream w is pattern w; for L2 the streams of patterns w and w + 1 are
+// (w, +M part), (w, total - M part), (w + 1, ...), (w + 1, ...).
+template <int MP, int KIND, int R>
+struct Bin32S {
+    static constexpr int NW = 1 << R;
+    static constexpr int K = (KIND == KIND_L2) ? 2 : 1;
+    static constexpr int RS = (MP + 15) & ~15;   // row stride of every table, dwords
+    static constexpr int N8 = (MP + 7) / 8;      // 8-column chunks of a row
+    static_assert(R >= 2, "four operand streams per group");
+
+    __device__ static constexpr uint32_t best_init() { return KIND == KIND_MARG ? 0x80000000u : 0u; }
+
+    __device__ static __forceinline__ uint32_t better(uint32_t a, uint32_t b)
+    {
+        if constexpr (KIND == KIND_MARG) return (uint32_t)max((int32_t)a, (int32_t)b);
+        else return max(a, b);
+    }
+
+    template <int S0, int S1, int S2, int S3, int C8>
+    __device__ static __forceinline__ void chunk4(const uint32_t (&s)[MP], uint64_t ob, uint32_t (&a)[4])
+    {
+        u32x8 o0, o1, o2, o3;
+        sload_4x8<(S0 * RS + 8 * C8) * 4, (S1 * RS + 8 * C8) * 4, (S2 * RS + 8 * C8) * 4,
+                  (S3 * RS + 8 * C8) * 4>(ob, o0, o1, o2, o3);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            constexpr int y0 = 8 * C8;
+            if (y0 + j >= MP) continue;
+            if (KIND == KIND_MARG && y0 + j == 0) {
+                // the linear column: s_0 - o_0 is the signed value itself
+                a[0] = s[0] - o0[0];
+                a[1] = s[0] - o1[0];
+                a[2] = s[0] - o2[0];
+                a[3] = s[0] - o3[0];
+                continue;
+            }
+            const uint32_t x = s[y0 + j];
+            a[0] = sad_u32_s(x, o0[j], a[0]);
+            a[1] = sad_u32_s(x, o1[j], a[1]);
+            a[2] = sad_u32_s(x, o2[j], a[2]);
+            a[3] = sad_u32_s(x, o3[j], a[3]);
+        }
+    }
+
+    __device__ static __forceinline__ void score(const uint32_t (&s)[MP], uint64_t ob, uint32_t& best)
+    {
+        if constexpr (KIND == KIND_L2) {
+            static_for<NW / 2>([&](auto h) {
+                constexpr int w = 2 * h;
+                uint32_t a[4] = {0, 0, 0, 0};
+                static_for<N8>([&](auto c) { chunk4<w, NW + w, w + 1, NW + w + 1, c>(s, ob, a); });
+                best = max(best, max(a[0] + a[1], a[2] + a[3]));
+            });
+        } else {
+            static_for<NW / 4>([&](auto g) {
+                constexpr int w = 4 * g;
+                uint32_t a[4] = {0, 0, 0, 0};
+                static_for<N8>([&](auto c) { chunk4<w, w + 1, w + 2, w + 3, c>(s, ob, a); });
+                if constexpr (KIND == KIND_MARG)
+                    best = (uint32_t)max(max((int32_t)best, max((int32_t)a[0], (int32_t)a[1])),
+                                         max((int32_t)a[2], (int32_t)a[3]));
+                else
+                    best = max(max(best, max(a[0], a[1])), max(a[2], a[3]));
+            });
+        }
+    }
+
+    // s += the row at `row` (RS dwords, wave-uniform address)
+    __device__ static __forceinline__ void add_row(uint32_t (&s)[MP], uint64_t row)
+    {
+        static_for<(N8 + 3) / 4>([&](auto q) {
+            constexpr int c0 = 4 * q;
+            constexpr int n = (N8 - c0) < 4 ? (N8 - c0) : 4;
+            u32x8 r[4];
+            if constexpr (n == 4)
+                sload_4x8<32 * c0, 32 * (c0 + 1), 32 * (c0 + 2), 32 * (c0 + 3)>(row, r[0], r[1], r[2], r[3]);
+            else if constexpr (n == 3) {
+                sload_2x8<32 * c0, 32 * (c0 + 1)>(row, r[0], r[1]);
+                sload_1x8<32 * (c0 + 2)>(row, r[2]);
+            } else if constexpr (n == 2)
+                sload_2x8<32 * c0, 32 * (c0 + 1)>(row, r[0], r[1]);
+            else
+                sload_1x8<32 * c0>(row, r[0]);
+#pragma unroll
+            for (int i = 0; i < n; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (8 * (c0 + i) + j < MP) s[8 * (c0 + i) + j] += r[i][j];
+        });
+    }
+
+    // Sweep one prefix value v: start state, then the Gray walk over 2^C words of
+    // the mid rows, scoring the 2^R low patterns at each word.
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, uint32_t& best)
+    {
+        cptr<uint32_t> base = as_const<uint32_t>(D.base);
+        cptr<int32_t> hid = as_const<int32_t>(D.hid);
+        uint32_t s[MP];
+#pragma unroll
+        for (int y = 0; y < MP; ++y) s[y] = base[y];
+        for (int h = 0; h < D.P; ++h) {
+            const uint32_t mask = 0u - (uint32_t)((v >> h) & 1u);
+#pragma unroll
+            for (int y = 0; y < MP; ++y) s[y] += mask & (uint32_t)hid[h * RS + y];
+        }
+        const uint64_t ob = (uint64_t)(uintptr_t)D.offs;
+        const uint64_t mb = (uint64_t)(uintptr_t)D.mid;
+        const uint32_t nsteps = 1u << D.C;
+        for (uint32_t t = 0;;) {
+            score(s, ob, best);
+            if (++t == nsteps) break;
+            const uint32_t k = brgc_changed(t);
+            const uint32_t g = brgc_digit(k, t);   // new value of digit k
+            add_row(s, mb + __builtin_amdgcn_readfirstlane((uint32_t)((2 * k + (1 - g)) * (RS * 4))));
         }
     }
 

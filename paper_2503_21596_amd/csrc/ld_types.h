@@ -54,6 +54,7 @@ struct Desc {
     const void* offs;
     const uint64_t* tab;
     int64_t* result;
+    int64_t* rec;       // if not null: rec[v - pfx_base] = best of prefix v (locating a maximiser)
 };
 
 // One unit of a device work queue: prefixes [p0, p0 + count) of problem `prob`.

@@ -82,6 +82,44 @@ def test_plan_marginal_rules():
     assert p["kind_name"] == "L_marg"
 
 
+def test_plan_reductions_worked_example(golden_dir):
+    """Sec. 2.1.1: the zero row goes and row 2 = 2 x row 1 merges into row 1,
+    leaving the printed 2 x 4 matrix.  For d >= 2 the row merge is allowed too
+    (c = 2 > 0, rule A3) and the three single-signed columns then unite into one
+    (Appendix A), so 2 rows and 2 columns remain and d = 2 needs no search."""
+    g = json.load(open(os.path.join(golden_dir, "preprocessing_example.json")))
+    M = np.array(g["matrix"], dtype=np.int32)
+    p = L.plan(M, 1, 0)
+    assert (p["n"], p["m"], p["transposed"]) == (2, 4, 0)
+    p2 = L.plan(M, 2, 0)
+    assert (p2["n"], p2["m"]) == (2, 2) and p2["kind_name"] == "sum|M|"
+
+
+def test_plan_reduction_rules():
+    base = np.array([[3, -1, 4, 1], [5, 9, -2, 6], [5, 3, 5, -8], [9, 7, 9, 3]], dtype=np.int32)
+    # a negative multiple of a row: merged for d = 1 (rule A1), kept for d >= 2 (A3)
+    M = np.vstack([base, -2 * base[1:2]]).astype(np.int32)
+    assert L.plan(M, 1, 0)["n"] == 4
+    assert L.plan(M, 3, 0)["n"] == 5
+    # a positive multiple: merged for every d
+    M = np.vstack([base, 3 * base[2:3]]).astype(np.int32)
+    assert L.plan(M, 1, 0)["n"] == 4 and L.plan(M, 3, 0)["n"] == 4
+    # a negative multiple of a column: merged for every d (rules A1, A2)
+    M = np.hstack([base, -base[:, 1:2]]).astype(np.int32)
+    assert L.plan(M, 1, 0)["m"] == 4 and L.plan(M, 3, 0)["m"] == 4
+    # single-signed columns (base column 0 and the two added) unite for d >= 2 only
+    # (Appendix A)
+    U = np.hstack([base, np.array([[1], [0], [2], [5]]), -np.array([[4], [1], [1], [0]])]).astype(np.int32)
+    assert L.plan(U, 1, 0)["m"] == 6
+    assert L.plan(U, 2, 0)["m"] == 4
+    # marginals: the first row and column take part in no merge (Sec. 2.2)
+    M = base.copy()
+    M[2] = 2 * M[0]
+    assert L.plan(M, 1, 1)["n"] == 4
+    M[3] = -M[1]
+    assert L.plan(M, 1, 1)["n"] == 3
+
+
 def test_plan_int64_boundary():
     # int32 path iff sum |M_xy| <= 2^31 - 1
     M = np.array([[2**30, 2**30 - 1], [0, 0]], dtype=np.int64)

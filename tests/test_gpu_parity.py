@@ -145,12 +145,60 @@ def test_sweep_shapes_agree():
     M = synth.matrix(11, 22, 30, -100, 100, "shape")
     want = oracle.l1(M)
     try:
-        for p_target, c_min, r_drop in [(20, 4, 0), (6, 10, 0), (12, 1, 1), (3, 4, 1)]:
-            L.set_sweep_shape(p_target, c_min, r_drop, 8)
+        for p_target, c_min, r_drop, sgpr_r in [(20, 4, 0, 4), (6, 10, 0, 5), (12, 1, 1, 0), (3, 4, 1, 0),
+                                                (3, 4, 0, 4)]:
+            L.set_sweep_shape(p_target, c_min, r_drop, 8, sgpr_r)
             assert L.ld_norm(M, 1, 0) == want
             assert L.ld_norm(M, 1, 1) == oracle.lmarg(M)
     finally:
-        L.set_sweep_shape(20, 4, 0, 8)
+        L.set_sweep_shape(20, 4, 0, 8, 4)
+
+
+def planted(seed, n, m):
+    """A random matrix with proportional rows and columns of both signs and some
+    single-signed columns: every reduction of the planner applies somewhere."""
+    M = synth.matrix(seed, n, m, -30, 30, "planted").astype(np.int64)
+    M[n - 1] = -2 * M[1]
+    M[n - 2] = 3 * M[2]
+    M[:, m - 1] = -M[:, 1]
+    M[:, m - 2] = 2 * M[:, 3]
+    M[:, 0] = np.abs(M[:, 0])
+    M[:, 4] = -np.abs(M[:, 4])
+    return M.astype(np.int32)
+
+
+@pytest.mark.parametrize("d,marg", [(1, 0), (1, 1), (2, 0), (3, 0), (4, 0)])
+def test_reductions_planted(d, marg):
+    """Proportional rows / columns (rules A1-A3) and single-signed columns
+    (Appendix A) are merged before the sweep; the values stay the oracle's."""
+    say("planted reductions", d, marg)
+    for i, (n, m) in enumerate([(8, 9), (11, 7), (13, 12), (6, 16)]):
+        M = planted(40 + i, n, m)
+        p = L.plan(M, d, marg)
+        assert p["n"] * p["m"] < n * m or p["kind_name"] in ("sum|M|", "zero")
+        check(M, d, marg)
+
+
+@pytest.mark.parametrize("sgpr_r", [0, 4, 5])
+def test_binary_kernel_variants(sgpr_r):
+    """Both int32 binary kernels (low-row operands in VGPRs, or streamed through
+    SGPRs with 4 or 5 low rows) against the oracle for L1, L_marg and L2, over
+    every column-chunk shape (m = 1 .. 64 in steps that hit each remainder mod 8)
+    and row counts below, at and above the low-row count."""
+    say("binary variants", sgpr_r)
+    try:
+        L.set_sweep_shape(0, 0, -1, 0, sgpr_r)
+        cases = [(n, m) for n, m in [(1, 5), (2, 3), (3, 8), (4, 1), (5, 17), (6, 64), (7, 63), (9, 42),
+                                     (12, 9), (13, 33), (14, 50), (15, 2), (16, 24), (11, 57)]]
+        for i, (n, m) in enumerate(cases):
+            M = synth.matrix(900 + i, n, m, -1000, 1000, "variants")
+            for d, marg in [(1, 0), (1, 1), (2, 0)]:
+                p = L.plan(M, d, marg)
+                if p["i64"] == 0 and sgpr_r and p["kind"] != 4 and p["mp"] <= 64 and p["n"] > 1:
+                    assert p["R"] == sgpr_r, p
+                check(M, d, marg)
+    finally:
+        L.set_sweep_shape(0, 0, -1, 0, 4)
 
 
 # ---------------------------------------------------------------------------

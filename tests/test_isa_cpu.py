@@ -1,0 +1,91 @@
+"""Checks on the gfx950 machine code of the built sweep kernels (our own build,
+disassembled with the ROCm LLVM tools; no GPU needed).
+
+The SGPR-operand kernels issue groups of scalar loads from inline assembly.  A
+scalar load writes its destination SGPRs some time after it issues, so a later
+load of the same group must not take its address from registers that an
+earlier, still outstanding load of the group writes: its address could change
+under it.  The compiler never emits that for its own loads; this test makes sure
+the register constraints of the hand-written groups rule it out as well."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+BUILD = os.path.join(ROOT, "paper_2503_21596_amd", "_build")
+LLVM = "/opt/rocm/llvm/bin"
+TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
+
+LOAD = re.compile(r"\s+s_load_dword\w*\s+s\[(\d+):(\d+)\],\s+s\[(\d+):(\d+)\]")
+LOAD1 = re.compile(r"\s+s_load_dword\s+s(\d+),\s+s\[(\d+):(\d+)\]")
+FUNC = re.compile(r"^[0-9a-f]+ <(\S+)>:")
+
+
+def _disassemble(obj, tmp_path):
+    fat = tmp_path / (os.path.basename(obj) + ".fatbin")
+    dev = tmp_path / (os.path.basename(obj) + ".gfx950.elf")
+    subprocess.run([f"{LLVM}/llvm-objcopy", f"--dump-section=.hip_fatbin={fat}", obj], check=True)
+    subprocess.run([f"{LLVM}/clang-offload-bundler", "--unbundle", "--type=o", f"--input={fat}",
+                    f"--targets={TARGET}", f"--output={dev}"], check=True)
+    r = subprocess.run([f"{LLVM}/llvm-objdump", "-d", "--mcpu=gfx950", str(dev)], check=True,
+                       capture_output=True, text=True)
+    return r.stdout.splitlines()
+
+
+def scan(lines):
+    """Scalar loads that read an address register written by an earlier scalar
+    load with no s_waitcnt in between.  Returns (function, line) pairs."""
+    bad = []
+    fn = None
+    pending = []          # destination ranges of loads issued since the last wait
+    for line in lines:
+        f = FUNC.match(line)
+        if f:
+            fn, pending = f.group(1), []
+            continue
+        if "s_waitcnt" in line or "s_endpgm" in line or "s_branch" in line or "s_cbranch" in line:
+            pending = []
+            continue
+        m = LOAD.match(line)
+        if m:
+            d0, d1, b0, b1 = map(int, m.groups())
+        else:
+            m1 = LOAD1.match(line)
+            if not m1:
+                continue
+            d0 = d1 = int(m1.group(1))
+            b0, b1 = int(m1.group(2)), int(m1.group(3))
+        if any(not (b1 < w0 or b0 > w1) for w0, w1 in pending):
+            bad.append((fn, line.strip()))
+        pending.append((d0, d1))
+    return bad
+
+
+def test_scan_catches_a_redirected_load():
+    """The scan flags the sequence the early-clobber constraints prevent."""
+    lines = ["0000000000000000 <k>:",
+             "\ts_load_dwordx8 s[36:43], s[36:37], 0x0",
+             "\ts_load_dwordx8 s[44:51], s[36:37], 0x20",
+             "\ts_waitcnt lgkmcnt(0)"]
+    assert len(scan(lines)) == 1
+    ok = ["0000000000000000 <k>:",
+          "\ts_load_dwordx8 s[36:43], s[52:53], 0x0",
+          "\ts_load_dwordx8 s[44:51], s[52:53], 0x20",
+          "\ts_waitcnt lgkmcnt(0)",
+          "\ts_load_dwordx2 s[52:53], s[52:53], 0x0"]
+    assert scan(ok) == []
+
+
+@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o"])
+def test_scalar_loads_keep_their_address(obj, tmp_path):
+    path = os.path.join(BUILD, obj)
+    if not os.path.exists(path):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    if not os.path.exists(f"{LLVM}/llvm-objdump"):
+        pytest.skip("ROCm LLVM tools not found")
+    lines = _disassemble(path, tmp_path)
+    assert sum(1 for l in lines if "s_load_dword" in l) > 100
+    bad = scan(lines)
+    assert not bad, bad[:5]
