@@ -32,7 +32,7 @@ def alg_ops_per_word(kind: str, m: int) -> int:
 
 
 KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip"]
-TRAFFIC_PROFILE = "profiles/k_bin32_l1_42x42.md"
+TRAFFIC_PROFILE = "profiles/k_bin32s_l1_42x42.md"
 
 
 def profiled_traffic():
@@ -234,9 +234,18 @@ def main():
         Mm = synth.config_42_marg(0)
         hm = L.Prepared(Mm, 1, 1)
         vm = hm.run(stream)
+        gm = json.load(open(gpath)).get("values", {}).get("marg_42") if os.path.exists(gpath) else None
         out["marg_42"] = {"value": vm, "seconds": hm.kernel_ms() / 1e3,
-                          "steps_per_s": hm.plan()["words"] / (hm.kernel_ms() / 1e3)}
+                          "steps_per_s": hm.plan()["words"] / (hm.kernel_ms() / 1e3),
+                          "matches_oracle": (vm == gm) if gm is not None else None}
         hm.close()
+        print("bench: argmax", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        va, av, bv = L.ld_argmax(M, 1, 0)
+        ta = time.perf_counter() - t0
+        attained = int(av.astype(np.int64) @ M.astype(np.int64) @ bv.astype(np.int64))
+        out["argmax_42"] = {"seconds": ta, "value": va, "attained": attained == va,
+                            "vs_value_pass": ta / (ms_per_step / 1e3)}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(M)
     h.close()

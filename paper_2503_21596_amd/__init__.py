@@ -14,6 +14,7 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libld.so")
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
 INT64_MIN = -(1 << 63)
 
 LD_OK, LD_EINVAL, LD_EMARG_D, LD_ETOOBIG, LD_EHIP, LD_EBUSY, LD_PENDING, LD_ENOTFOUND, LD_ECANCELED = range(9)
@@ -109,6 +110,10 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)   # a missing export is a broken build: raise
             f.restype = res
             f.argtypes = args
+        # the shapes the autotuner measured on MI355X (its JSON, kept with the
+        # package; the library's built-in defaults are the same values)
+        if os.path.exists(TUNING_PATH) and os.environ.get("LD_TUNING", "1") != "0":
+            L.ld_load_tuning(TUNING_PATH.encode())
         _lib = L
     return _lib
 

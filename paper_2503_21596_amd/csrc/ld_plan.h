@@ -26,7 +26,7 @@ struct SweepShape {
                              // rest of the rows become prefix rows (batch planning)
     int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
-    int sgpr_r = 4;            // int32 binary kinds: low rows of the SGPR-operand kernel
+    int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)

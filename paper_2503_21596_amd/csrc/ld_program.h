@@ -57,12 +57,13 @@ struct ItemShape {
 };
 
 // queue items of a single-problem launch: about 2^22 words each (pops stay rare
-// next to the work), at least two per resident wave
+// next to the work), at least two per resident wave (the SGPR-operand kernels
+// hold seven waves per SIMD: 7168 on 256 CUs)
 inline ItemShape plain_item_shape()
 {
     ItemShape s;
     s.item_words = (double)(1u << 22);
-    s.min_items = 4096;
+    s.min_items = 16384;
     return s;
 }
 

@@ -520,7 +520,9 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
     }
     Request* r = new Request;
     r->t_submit = now_s();
-    r->plan = make_plan(p->M, p->n, p->m, p->d, p->marginals, batch_shape_for(p->n, p->m, p->d));
+    // the shape of a plain call: requests mostly run a few at a time, so a large
+    // one must be able to fill the device by itself (a batch shape caps its lanes)
+    r->plan = make_plan(p->M, p->n, p->m, p->d, p->marginals, get_shape());
     if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO) {
         if (r->plan.kind == PK_SUMABS) {
             r->is_sum = true;

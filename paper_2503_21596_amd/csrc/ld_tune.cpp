@@ -101,9 +101,9 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
     std::fprintf(f,
                  "{\n  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
-                 "  \"plain_r_drop\": %d,\n  \"measured\": [%s]\n}\n",
+                 "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"plain_p_min\": %d,\n  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
-                 t.plain_r_drop, notes.c_str());
+                 t.plain_r_drop, t.sgpr_r, t.plain_p_min, notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -134,8 +134,10 @@ void set_tuning(const Tuning& t)
     }
     SweepShape s = get_shape();
     s.p_target = t.plain_p_target;
+    s.p_min = std::min(t.plain_p_min, t.plain_p_target);
     s.c_goal = t.plain_c_goal;
     s.r_drop = t.plain_r_drop;
+    s.sgpr_r = t.sgpr_r;
     set_shape(s);
 }
 
@@ -182,10 +184,10 @@ int ld_autotune(const char* path, double budget_seconds)
 
     // batch shape: words per prefix (binary and d-ary), prefixes per problem and
     // words per queue item
-    const Cal cal = calibration_batch(256, 0x5eed);
+    const Cal cal = calibration_batch(1024, 0x5eed);
     double best_t = 1e30;
     for (int c : {8, 10, 12})
-        for (int cap : {10, 12, 14})
+        for (int cap : {0, 16})
             for (double w : {65536.0, 262144.0}) {
                 if (now_s() > t_end) break;
                 Tuning t = best;
@@ -206,8 +208,9 @@ int ld_autotune(const char* path, double budget_seconds)
             }
     set_tuning(best);
 
-    // plain calls: lane range and words per prefix, timed on a 30 x 40 and a
-    // 35 x 42 L1 problem (sum of the two times)
+    // plain calls: kernel variant (low rows of the SGPR-operand kernel, or the
+    // VGPR-operand kernel), lane range and words per prefix, timed on a 30 x 40
+    // and a 35 x 42 L1 problem (sum of the two times)
     {
         Rng r{0xca1};
         std::vector<int32_t> A((size_t)30 * 40), B((size_t)35 * 42);
@@ -215,21 +218,27 @@ int ld_autotune(const char* path, double budget_seconds)
         for (auto& v : B) v = r.uniform(-100, 100);
         double bt = 1e30;
         Tuning bp = best;
-        for (int p : {18, 20, 22})
-            for (int c : {12, 14, 16}) {
-                if (now_s() > t_end) break;
-                Tuning t = best;
-                t.plain_p_target = p;
-                t.plain_c_goal = c;
-                set_tuning(t);
-                const double dt = time_plain(A, 30, 40) + time_plain(B, 35, 42);
-                std::snprintf(buf, sizeof buf, ", {\"plain_p\": %d, \"c_goal\": %d, \"ms\": %.3f}", p, c, 1e3 * dt);
-                notes += buf;
-                if (dt < bt) {
-                    bt = dt;
-                    bp = t;
-                }
-            }
+        for (int sr : {5, 4, 0})
+            for (int pm : {16, 18, 19})
+                for (int p : {20, 22})
+                    for (int c : {12, 14}) {
+                        if (now_s() > t_end) break;
+                        Tuning t = best;
+                        t.sgpr_r = sr;
+                        t.plain_p_min = pm;
+                        t.plain_p_target = p;
+                        t.plain_c_goal = c;
+                        set_tuning(t);
+                        const double dt = time_plain(A, 30, 40) + time_plain(B, 35, 42);
+                        std::snprintf(buf, sizeof buf,
+                                      ", {\"sgpr_r\": %d, \"p_min\": %d, \"plain_p\": %d, \"c_goal\": %d, \"ms\": %.3f}",
+                                      sr, pm, p, c, 1e3 * dt);
+                        notes += buf;
+                        if (dt < bt) {
+                            bt = dt;
+                            bp = t;
+                        }
+                    }
         best = bp;
     }
     set_tuning(best);
@@ -259,8 +268,10 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "item_words", &v)) t.item_words = std::max(1.0, v);
     if (read_key(text, "batch_pfx_cap", &v)) t.batch_pfx_cap = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_p_target", &v)) t.plain_p_target = std::max(0, std::min(40, (int)v));
+    if (read_key(text, "plain_p_min", &v)) t.plain_p_min = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_c_goal", &v)) t.plain_c_goal = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
+    if (read_key(text, "sgpr_r", &v)) t.sgpr_r = (v == 4 || v == 5) ? (int)v : 0;
     set_tuning(t);
     return LD_OK;
 }

@@ -151,7 +151,7 @@ def test_sweep_shapes_agree():
             assert L.ld_norm(M, 1, 0) == want
             assert L.ld_norm(M, 1, 1) == oracle.lmarg(M)
     finally:
-        L.set_sweep_shape(20, 4, 0, 8, 4)
+        L.set_sweep_shape(20, 4, 0, 8, 5)
 
 
 def planted(seed, n, m):
@@ -198,7 +198,7 @@ def test_binary_kernel_variants(sgpr_r):
                     assert p["R"] == sgpr_r, p
                 check(M, d, marg)
     finally:
-        L.set_sweep_shape(0, 0, -1, 0, 4)
+        L.set_sweep_shape(0, 0, -1, 0, 5)
 
 
 # ---------------------------------------------------------------------------
