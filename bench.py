@@ -102,8 +102,8 @@ def bench_batch(L, synth, seed: int = 0):
 
 def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0):
     """Poisson request stream into the server (continuous batching) against the same
-    trace served by sequential plain calls (FIFO; queueing from the measured
-    service times)."""
+    trace replayed in real time through sequential plain calls (first come, first
+    served, so queueing is included)."""
     import numpy as np
     reqs = synth.served_requests(seed, count=count, rate=rate)
     S = L.Server()
@@ -120,23 +120,26 @@ def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0)
     S.close()
     served = {"requests": count, "rate_per_s": rate, "solves_per_s": count / (t_end - t_start),
               "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-              "launches": st["launches"]}
-    # sequential plain calls: service times, then a FIFO queue over the arrival times
+              "mean_wait_ms": st["mean_wait_ms"], "launches": st["launches"]}
+    # the same trace in real time through sequential plain calls: one thread waits
+    # for each arrival (when idle) and serves the requests first come, first served
     durs = []
     seq_vals = []
-    for _, M, d in reqs:
+    lat = []
+    t_start = time.perf_counter()
+    for t_arr, M, d in reqs:
+        delay = t_start + t_arr - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
         t0 = time.perf_counter()
         seq_vals.append(L.ld_norm(M, d, 0))
-        durs.append(time.perf_counter() - t0)
-    free_at = 0.0
-    lat = []
-    for (t_arr, _, _), dur in zip(reqs, durs):
-        start = max(t_arr, free_at)
-        free_at = start + dur
-        lat.append(free_at - t_arr)
+        t1 = time.perf_counter()
+        durs.append(t1 - t0)
+        lat.append(t1 - (t_start + t_arr))
+    t_end = time.perf_counter()
     lat = np.array(lat) * 1e3
-    seq = {"solves_per_s": count / max(free_at, reqs[-1][0]), "p50_ms": float(np.percentile(lat, 50)),
-           "p99_ms": float(np.percentile(lat, 99)), "busy_s": float(sum(durs))}
+    seq = {"solves_per_s": count / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "busy_s": float(sum(durs))}
     return {"served": served, "sequential_plain": seq, "identical": vals == seq_vals,
             "offered_load_of_sequential": float(sum(durs)) / reqs[-1][0]}
 
@@ -231,6 +234,7 @@ def main():
         out["batched_vs_plain"] = bench_batch(L, synth)
         print("bench: serve", file=sys.stderr, flush=True)
         out["served"] = bench_serve(L, synth)
+        out["served_600"] = bench_serve(L, synth, seed=1, count=3000, rate=600.0)
         Mm = synth.config_42_marg(0)
         hm = L.Prepared(Mm, 1, 1)
         vm = hm.run(stream)

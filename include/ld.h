@@ -154,16 +154,19 @@ typedef struct {
     uint64_t arena_bytes;           /* device bytes for problem tables (0: 256 MiB)        */
     int32_t max_inflight_problems;  /* result slots (0: 1024)                              */
     int32_t max_items_per_launch;   /* cap on one step's items (0: 65536)                  */
-    double words_per_item;          /* queue-item size (0: the tuned batch value)           */
-    double step_ms;                 /* device work per step (0: 4 ms)                       */
+    double words_per_item;          /* queue-item size (0: 2^17 words)                      */
+    double step_ms;                 /* device work per bulk step (0: 4 ms)                  */
     int32_t max_queued;             /* submitted but not admitted; beyond: LD_EBUSY (0: 65536) */
     int32_t device;                 /* HIP device index                                     */
+    double express_ms;              /* requests below this estimated device time take the
+                                       express lane (0: 0.25 ms; negative: no express lane) */
 } ld_server_config;
 
 typedef struct {
     uint64_t submitted, completed, rejected, launches, items;
     int32_t inflight, queued;
     double p50_ms, p99_ms, mean_ms;  /* latency: submit -> completion seen by the scheduler */
+    double mean_wait_ms;             /* mean of submit -> first step issued                  */
 } ld_stats;
 
 typedef struct ld_server ld_server;

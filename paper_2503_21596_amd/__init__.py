@@ -44,7 +44,8 @@ class ld_plan_info(ctypes.Structure):
 class ld_server_config(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight_problems", ctypes.c_int32),
                 ("max_items_per_launch", ctypes.c_int32), ("words_per_item", ctypes.c_double),
-                ("step_ms", ctypes.c_double), ("max_queued", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("step_ms", ctypes.c_double), ("max_queued", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("express_ms", ctypes.c_double)]
 
 
 class ld_stats(ctypes.Structure):
@@ -52,7 +53,7 @@ class ld_stats(ctypes.Structure):
                 ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("items", ctypes.c_uint64), ("inflight", ctypes.c_int32),
                 ("queued", ctypes.c_int32), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("mean_ms", ctypes.c_double)]
+                ("mean_ms", ctypes.c_double), ("mean_wait_ms", ctypes.c_double)]
 
 
 # exported symbols and their signatures: name -> (restype, argtypes)
@@ -306,9 +307,9 @@ class Server:
 
     def __init__(self, arena_bytes: int = 256 << 20, max_inflight_problems: int = 1024,
                  max_items_per_launch: int = 65536, words_per_item: float = 0.0, step_ms: float = 0.0,
-                 max_queued: int = 0, device: int = 0):
+                 max_queued: int = 0, device: int = 0, express_ms: float = 0.0):
         cfg = ld_server_config(arena_bytes, max_inflight_problems, max_items_per_launch, words_per_item,
-                               step_ms, max_queued, device)
+                               step_ms, max_queued, device, express_ms)
         self._h = lib().ld_server_create(ctypes.byref(cfg))
         if not self._h:
             raise _err()

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void k_bin32(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = B::finish(pb);
         }
         wb.add(B::finish(best));
+        wb.item_end(q);
     }
     wb.flush();
 }
@@ -65,6 +66,7 @@ __global__ __launch_bounds__(256) void k_bin32s(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = B::finish(pb);
         }
         wb.add(B::finish(best));
+        wb.item_end(q);
     }
     wb.flush();
 }
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(256) void k_bin64(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(B::finish(best));
+        wb.item_end(q);
     }
     wb.flush();
 }

@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void k_dary32(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = (int64_t)pb;
         }
         wb.add((int64_t)best);
+        wb.item_end(q);
     }
     wb.flush();
 }
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(256) void k_dary64(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(best);
+        wb.item_end(q);
     }
     wb.flush();
 }
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(64) void k_wide(QArgs q)
             if (D.rec) D.rec[it.p0 + i] = pb;
         }
         wb.add(best);
+        wb.item_end(q);
     }
     wb.flush();
 }
@@ -133,13 +136,18 @@ __global__ __launch_bounds__(256) void k_scatter(const ScatterOp* __restrict__ o
     }
 }
 
-// Server steps: result slots of newly admitted problems to INT64_MIN, the step's
-// queue heads to 0.
+// Server steps: result slots of newly admitted problems to INT64_MIN and their
+// unfinished-item counters to their item counts; the step's queue heads to 0.
 __global__ __launch_bounds__(256) void k_reset_slots(int64_t* __restrict__ results, const uint32_t* __restrict__ slots,
-                                                     uint32_t n_slots, uint32_t* __restrict__ heads, uint32_t n_heads)
+                                                     const uint32_t* __restrict__ counts, uint32_t n_slots,
+                                                     uint32_t* __restrict__ left, uint32_t* __restrict__ heads,
+                                                     uint32_t n_heads)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += stride) results[slots[i]] = INT64_MIN;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += stride) {
+        results[slots[i]] = INT64_MIN;
+        left[slots[i]] = counts[i];
+    }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
 }
 

@@ -11,8 +11,17 @@
 //   4. enqueues: one upload of the step buffer (new tables, descriptors, items),
 //      a scatter kernel, a slot and head reset, one persistent queue launch per
 //      kernel shape, and the copy of all result slots to pinned memory.
-// At most two steps are in flight, so a request that arrives while others run is
-// swept in the next step.  Result slots keep partial maxima between steps.
+// At most two steps are in flight per lane, so a request that arrives while
+// others run is swept in the next step.  Result slots keep partial maxima between
+// steps.  A bulk request completes when the step with its last items retires; an
+// express request as soon as its last item ends (that wave reports the value in
+// a host-mapped record, without waiting for the rest of its step).
+//
+// There are two lanes, each with its own stream and steps: bulk and express.  A
+// request of less than about a quarter of a millisecond of work goes to the
+// express lane, whose launches take at most one block per CU; bulk launches leave
+// one block per CU free (when their kernel fits three or more per CU), so express
+// work starts at once instead of queueing behind bulk steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,18 +53,22 @@ double now_s()
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// sustained VALU rate used to size a step (ops/s); only the step length depends on it
+// Sustained VALU rate used to size steps (lane-ops/s); only step lengths depend
+// on it.  Item costs (split_items) count the ops of one lane of the wave that runs
+// the item, so an item occupies the device for about cost x 64 lane-ops.
 constexpr double STEP_OPS_PER_S = 3.0e13;
+constexpr double COST_UNITS_PER_S = STEP_OPS_PER_S / 64.0;
 
 struct Request {
     uint64_t ticket = 0;
     Plan plan;
-    double t_submit = 0, t_done = 0;
+    double t_submit = 0, t_done = 0, t_issue = 0;
     int status = LD_PENDING;
     int64_t value = 0;
     // scheduling state
     int slot = -1;
     size_t arena_off = 0, arena_size = 0;
+    bool tracked = false;            // completes through its host-mapped record
     std::vector<Item> items;         // sorted longest first
     std::vector<double> cost;
     size_t next = 0;                 // first item not yet issued
@@ -64,6 +77,7 @@ struct Request {
     bool uploaded = false;
     bool canceled = false;
     bool is_sum = false;
+    int lane = 0;                    // 0 bulk, 1 express
 };
 
 // first-fit allocator over [0, size)
@@ -110,18 +124,30 @@ struct Step {
     std::vector<std::pair<Request*, uint32_t>> issued;   // request, items in this step
 };
 
+struct Lane {
+    hipStream_t stream = nullptr;
+    Step steps[2];
+    int next_step = 0;
+    std::deque<Request*> pending;   // submitted, not admitted (FIFO)
+};
+
+constexpr int BULK = 0, EXPRESS = 1;
+
 }  // namespace
 
 struct ld_server {
     ld_server_config cfg{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    int cus = 0;                      // compute units of the device
+    double express_cost = 0;          // request cost (item-cost units) below which it is express
     uint8_t* arena_dev = nullptr;
     Desc* d_descs = nullptr;
     int64_t* d_results = nullptr;
+    uint32_t* d_left = nullptr;      // per slot: items of the request not yet finished
+    DoneRec* done_host = nullptr;    // per slot: completion record (host-mapped)
+    DoneRec* done_dev = nullptr;     // the same memory as the kernels address it
     size_t step_bytes = 0;
-    Step steps[2];
-    int next_step = 0;
+    Lane lanes[2];
     Arena arena;
     std::vector<int> free_slots;
     std::vector<Request*> slots;
@@ -129,7 +155,6 @@ struct ld_server {
     std::mutex mu;
     std::condition_variable cv;       // scheduler wake-up
     std::condition_variable done_cv;  // request completion
-    std::deque<Request*> pending;
     std::unordered_map<uint64_t, Request*> all;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -138,19 +163,25 @@ struct ld_server {
 
     uint64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_launches = 0, st_items = 0;
     std::vector<double> latencies_ms;
+    double wait_sum_ms = 0;
+    uint64_t wait_n = 0;
 
     ~ld_server()
     {
-        for (auto& s : steps) {
-            if (s.ev) (void)hipEventDestroy(s.ev);
-            if (s.host) (void)hipHostFree(s.host);
-            if (s.dev) (void)hipFree(s.dev);
-            if (s.hres) (void)hipHostFree(s.hres);
+        for (auto& ln : lanes) {
+            for (auto& s : ln.steps) {
+                if (s.ev) (void)hipEventDestroy(s.ev);
+                if (s.host) (void)hipHostFree(s.host);
+                if (s.dev) (void)hipFree(s.dev);
+                if (s.hres) (void)hipHostFree(s.hres);
+            }
+            if (ln.stream) (void)hipStreamDestroy(ln.stream);
         }
         if (arena_dev) (void)hipFree(arena_dev);
         if (d_descs) (void)hipFree(d_descs);
         if (d_results) (void)hipFree(d_results);
-        if (stream) (void)hipStreamDestroy(stream);
+        if (d_left) (void)hipFree(d_left);
+        if (done_host) (void)hipHostFree(done_host);
         for (auto& kv : all) delete kv.second;
     }
 };
@@ -188,15 +219,13 @@ void release_slot(ld_server* S, Request* r)
     }
 }
 
-// Retire the oldest busy step if it has finished (wait: block until it has).
-bool retire(ld_server* S, bool wait)
+// Retire the oldest busy step of a lane if it has finished.
+bool retire(ld_server* S, Lane& L)
 {
     for (int k = 0; k < 2; ++k) {
-        Step& st = S->steps[(S->next_step + k) % 2];
+        Step& st = L.steps[(L.next_step + k) % 2];
         if (!st.busy) continue;
-        if (wait) {
-            if (hipEventSynchronize(st.ev) != hipSuccess) return false;
-        } else {
+        {
             const hipError_t q = hipEventQuery(st.ev);
             if (q == hipErrorNotReady) return true;
             if (q != hipSuccess) return false;
@@ -204,11 +233,12 @@ bool retire(ld_server* S, bool wait)
         std::lock_guard<std::mutex> g(S->mu);
         for (auto& [r, n] : st.issued) {
             r->outstanding -= n;
-            if (r->outstanding == 0 && r->next >= r->items.size()) {
+            // (a request that completed through its record has no items left)
+            if (r->outstanding == 0 && r->next >= r->items.size() && r->slot >= 0) {
                 const int slot = r->slot;
                 const int64_t v = st.hres[slot];
                 release_slot(S, r);
-                finish(S, r, r->canceled ? LD_ECANCELED : LD_OK, v);
+                if (r->status == LD_PENDING) finish(S, r, r->canceled ? LD_ECANCELED : LD_OK, v);
             }
         }
         st.issued.clear();
@@ -218,13 +248,14 @@ bool retire(ld_server* S, bool wait)
     return true;
 }
 
-int busy_steps(ld_server* S) { return (int)S->steps[0].busy + (int)S->steps[1].busy; }
+int busy_steps(const Lane& L) { return (int)L.steps[0].busy + (int)L.steps[1].busy; }
 
-// Build and enqueue one step on S->steps[S->next_step].  Returns false on a HIP error.
-bool issue_step(ld_server* S, bool* issued_any)
+// Build and enqueue one step of lane `li`.  Returns false on a HIP error.
+bool issue_step(ld_server* S, int li, bool* issued_any)
 {
     *issued_any = false;
-    Step& st = S->steps[S->next_step];
+    Lane& L = S->lanes[li];
+    Step& st = L.steps[L.next_step];
     if (st.busy) return true;
     const int max_slots = S->cfg.max_inflight_problems;
     std::vector<Request*> admitted;
@@ -233,12 +264,12 @@ bool issue_step(ld_server* S, bool* issued_any)
         std::lock_guard<std::mutex> g(S->mu);
         // 2. admission by slot and arena space (FIFO; a request too big for the
         // free arena waits and holds back the ones behind it)
-        while (!S->pending.empty() && !S->free_slots.empty()) {
-            Request* r = S->pending.front();
+        while (!L.pending.empty() && !S->free_slots.empty()) {
+            Request* r = L.pending.front();
             const size_t bytes = align256(std::max<size_t>(r->plan.blob.size(), 256));
             size_t off;
             if (!S->arena.alloc(bytes, &off)) break;
-            S->pending.pop_front();
+            L.pending.pop_front();
             r->arena_off = off;
             r->arena_size = bytes;
             r->slot = S->free_slots.back();
@@ -249,9 +280,9 @@ bool issue_step(ld_server* S, bool* issued_any)
         // 3. items: smallest remaining work first, up to the step budget
         std::vector<Request*> live;
         for (Request* r : S->slots)
-            if (r && r->next < r->items.size()) live.push_back(r);
+            if (r && r->lane == li && r->next < r->items.size()) live.push_back(r);
         std::sort(live.begin(), live.end(), [](Request* a, Request* b) { return a->remaining < b->remaining; });
-        const double budget = STEP_OPS_PER_S * S->cfg.step_ms * 1e-3;
+        const double budget = COST_UNITS_PER_S * S->cfg.step_ms * 1e-3;
         double used = 0;
         size_t n_items = 0;
         for (Request* r : live) {
@@ -268,6 +299,11 @@ bool issue_step(ld_server* S, bool* issued_any)
                 ++n_items;
             }
             if (!take.empty()) {
+                if (r->t_issue == 0) {
+                    r->t_issue = now_s();
+                    S->wait_sum_ms += 1e3 * (r->t_issue - r->t_submit);
+                    S->wait_n++;
+                }
                 r->outstanding += (uint32_t)take.size();
                 picks.push_back({r, std::move(take)});
             }
@@ -313,6 +349,8 @@ bool issue_step(ld_server* S, bool* issued_any)
         off = align256(off + sizeof(Desc));
     }
     const size_t off_slots = off;
+    off = align256(off + 4 * admitted.size());
+    const size_t off_counts = off;
     off = align256(off + 4 * admitted.size());
     std::vector<std::pair<size_t, size_t>> gpos;   // items offset, count per group
     for (auto& g : groups) {
@@ -360,6 +398,11 @@ bool issue_step(ld_server* S, bool* issued_any)
         ops.push_back({D + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
         const uint32_t slot = (uint32_t)r->slot;
         std::memcpy(H + off_slots + 4 * k, &slot, 4);
+        const uint32_t count = r->is_sum ? 0u : (uint32_t)r->items.size();
+        std::memcpy(H + off_counts + 4 * k, &count, 4);
+        // the completion record starts clear (nothing can write it: the slot was free)
+        __atomic_store_n(&S->done_host[slot].flag, 0u, __ATOMIC_RELEASE);
+        r->tracked = !r->is_sum && r->lane == EXPRESS;
     }
     if (!ops.empty()) std::memcpy(H + off_ops, ops.data(), sizeof(ScatterOp) * ops.size());
     size_t gi = 0;
@@ -371,7 +414,7 @@ bool issue_step(ld_server* S, bool* issued_any)
     if (!sums.empty()) std::memcpy(H + off_sums, sums.data(), sizeof(SumItem) * sums.size());
 
     // 4. enqueue
-    hipStream_t s = S->stream;
+    hipStream_t s = L.stream;
     bool ok = hipMemcpyAsync(D, H, off, hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok && !ops.empty()) {
         const ScatterOp* dops = (const ScatterOp*)(D + off_ops);
@@ -383,9 +426,12 @@ bool issue_step(ld_server* S, bool* issued_any)
     uint32_t* dheads = (uint32_t*)(D + off_heads);
     if (ok && !admitted.empty()) {
         const uint32_t* dslots = (const uint32_t*)(D + off_slots);
+        const uint32_t* dcounts = (const uint32_t*)(D + off_counts);
         uint32_t ns = (uint32_t)admitted.size(), nh = 0;
         int64_t* dres = S->d_results;
-        void* args[] = {(void*)&dres, (void*)&dslots, (void*)&ns, (void*)&dheads, (void*)&nh};
+        uint32_t* dleft = S->d_left;
+        void* args[] = {(void*)&dres, (void*)&dslots, (void*)&dcounts, (void*)&ns, (void*)&dleft, (void*)&dheads,
+                        (void*)&nh};
         ok = hipLaunchKernel(kernel_reset_slots(), dim3(std::max<uint32_t>(1, std::min<uint32_t>(64, (ns + 255) / 256))),
                              dim3(256), args, 0, s) == hipSuccess;
     }
@@ -394,13 +440,25 @@ bool issue_step(ld_server* S, bool* issued_any)
     for (auto& g : groups) {
         QArgs q{};   // explicit items (several problems per launch)
         q.descs = S->d_descs;
+        if (li == EXPRESS) {
+            // small requests report their value as soon as their last item ends.
+            // (Not for bulk work: its many items would all count down one counter,
+            // and atomics on one address from every XCD serialize.)
+            q.left = S->d_left;
+            q.done = S->done_dev;
+        }
         q.items = (const Item*)(D + gpos[gi].first);
         q.n_items = (uint32_t)gpos[gi].second;
         q.head = dheads + gi;
         const uint32_t threads = g.first.second ? 64 : 256;
         const size_t lds = group_lds[g.first];
         const uint32_t want = (q.n_items + threads / 64 - 1) / (threads / 64);
-        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, resident_blocks(g.first.first, threads, lds)));
+        const uint32_t resident = resident_blocks(g.first.first, threads, lds);
+        const uint32_t per_cu = S->cus > 0 ? resident / (uint32_t)S->cus : 0;
+        uint32_t cap = resident;
+        if (li == EXPRESS) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
+        else if (per_cu >= 3) cap = resident - (uint32_t)S->cus;   // one block per CU for express work
+        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, cap));
         void* args[] = {(void*)&q};
         ok = ok && hipLaunchKernel(g.first.first, dim3(blocks), dim3(threads), args, lds, s) == hipSuccess;
         n_items += q.n_items;
@@ -422,37 +480,62 @@ bool issue_step(ld_server* S, bool* issued_any)
         S->st_items += n_items;
     }
     st.busy = true;
-    S->next_step = 1 - S->next_step;
+    L.next_step = 1 - L.next_step;
     *issued_any = true;
     return ok;
+}
+
+// Requests whose last item has ended report through their host-mapped record;
+// complete them without waiting for the rest of their step (mu held).  Their slot
+// is released when the step retires.
+void poll_done(ld_server* S)
+{
+    for (Request* r : S->slots) {
+        if (!r || !r->tracked || r->status != LD_PENDING) continue;
+        const DoneRec& d = S->done_host[r->slot];
+        if (__atomic_load_n(&d.flag, __ATOMIC_ACQUIRE) == 0) continue;
+        const int64_t v = __atomic_load_n(&d.value, __ATOMIC_RELAXED);
+        finish(S, r, r->canceled ? LD_ECANCELED : LD_OK, v);
+    }
 }
 
 void scheduler(ld_server* S)
 {
     (void)hipSetDevice(S->device);
+    auto busy_all = [&]() { return busy_steps(S->lanes[BULK]) + busy_steps(S->lanes[EXPRESS]); };
     for (;;) {
-        bool have_work;
+        bool have_work[2];
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            auto work_left = [&]() {
-                if (!S->pending.empty() && !S->free_slots.empty()) return true;
+            auto work_left = [&](int li) {
+                if (!S->lanes[li].pending.empty() && !S->free_slots.empty()) return true;
                 for (Request* r : S->slots)
-                    if (r && r->next < r->items.size()) return true;
+                    if (r && r->lane == li && r->next < r->items.size()) return true;
                 return false;
             };
-            if (busy_steps(S) == 0) {
-                S->cv.wait(lk, [&]() { return S->stop || work_left(); });
-                if (S->stop && !work_left()) return;
+            auto any_work = [&]() { return work_left(BULK) || work_left(EXPRESS); };
+            poll_done(S);
+            if (busy_all() == 0) {
+                S->cv.wait(lk, [&]() { return S->stop || any_work(); });
+                if (S->stop && !any_work()) return;
             }
-            have_work = work_left();
+            have_work[BULK] = work_left(BULK);
+            have_work[EXPRESS] = work_left(EXPRESS);
         }
-        if (!retire(S, false)) break;
-        bool issued = false;
-        if (have_work && busy_steps(S) < 2) {
-            if (!issue_step(S, &issued)) break;
+        bool ok = true, issued = false;
+        for (int li : {EXPRESS, BULK}) {
+            Lane& L = S->lanes[li];
+            ok = ok && retire(S, L);
+            bool one = false;
+            if (ok && have_work[li] && busy_steps(L) < 2) ok = issue_step(S, li, &one);
+            issued = issued || one;
         }
-        if (!issued && busy_steps(S) > 0) {
-            if (!retire(S, true)) break;
+        if (!ok) break;
+        if (!issued && busy_all() > 0) {
+            // steps in flight and nothing to add: poll again at once for finished
+            // requests and steps (the device writes completion records to host
+            // memory; a timed wait would add the timer's slack to every latency)
+            std::this_thread::yield();
         }
     }
     // a HIP failure: fail everything still open
@@ -473,31 +556,59 @@ ld_server* ld_server_create(const ld_server_config* cfg_in)
     if (!cfg.arena_bytes) cfg.arena_bytes = (uint64_t)256 << 20;
     if (cfg.max_inflight_problems <= 0) cfg.max_inflight_problems = 1024;
     if (cfg.max_items_per_launch <= 0) cfg.max_items_per_launch = 65536;
-    if (cfg.words_per_item <= 0) cfg.words_per_item = get_tuning().item_words;
+    if (cfg.words_per_item <= 0) cfg.words_per_item = (double)(1 << 17);
     if (cfg.step_ms <= 0) cfg.step_ms = 4.0;
+    if (cfg.express_ms == 0) cfg.express_ms = 0.25;
     if (cfg.max_queued <= 0) cfg.max_queued = 65536;
     ld_server* S = new ld_server;
     S->cfg = cfg;
+    S->express_cost = COST_UNITS_PER_S * cfg.express_ms * 1e-3;
     S->device = cfg.device;
     int count = 0;
     bool ok = hipGetDeviceCount(&count) == hipSuccess && cfg.device >= 0 && cfg.device < count &&
               hipSetDevice(cfg.device) == hipSuccess && device_ok(nullptr);
-    ok = ok && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+    for (auto& ln : S->lanes) ok = ok && hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess;
+    {
+        hipDeviceProp_t prop;
+        ok = ok && hipGetDeviceProperties(&prop, cfg.device) == hipSuccess;
+        if (ok) S->cus = prop.multiProcessorCount;
+    }
     ok = ok && hipMalloc((void**)&S->arena_dev, cfg.arena_bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&S->d_descs, sizeof(Desc) * cfg.max_inflight_problems) == hipSuccess;
     ok = ok && hipMalloc((void**)&S->d_results, 8 * (size_t)cfg.max_inflight_problems) == hipSuccess;
+    ok = ok && hipMalloc((void**)&S->d_left, 4 * (size_t)cfg.max_inflight_problems) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&S->done_host, sizeof(DoneRec) * cfg.max_inflight_problems,
+                             hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+    ok = ok && hipHostGetDevicePointer((void**)&S->done_dev, S->done_host, 0) == hipSuccess;
+    if (ok) std::memset(S->done_host, 0, sizeof(DoneRec) * cfg.max_inflight_problems);
     // a step uploads at most every slot's tables and descriptors plus its items
     S->step_bytes = align256(sizeof(ScatterOp) * 2 * cfg.max_inflight_problems) + cfg.arena_bytes +
                     align256(256 + sizeof(Desc)) * (size_t)cfg.max_inflight_problems +
                     align256(4 * (size_t)cfg.max_inflight_problems) +
                     align256(sizeof(Item) * (size_t)cfg.max_items_per_launch) + 256 * 64 +
                     align256(sizeof(SumItem) * (size_t)cfg.max_inflight_problems) + (1 << 16);
-    for (auto& st : S->steps) {
+    for (auto& ln : S->lanes)
+    for (auto& st : ln.steps) {
         ok = ok && hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) == hipSuccess;
         ok = ok && hipHostMalloc((void**)&st.host, S->step_bytes, hipHostMallocDefault) == hipSuccess;
         ok = ok && hipMalloc((void**)&st.dev, S->step_bytes) == hipSuccess;
         ok = ok && hipHostMalloc((void**)&st.hres, 8 * (size_t)cfg.max_inflight_problems, hipHostMallocDefault) ==
                        hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        delete S;
+        set_error(LD_EHIP);
+        return nullptr;
+    }
+    // first use of a stream sets up its hardware queue (milliseconds): do it now,
+    // not in the first request's latency
+    for (auto& ln : S->lanes) {
+        unsigned long long* dummy = (unsigned long long*)ln.steps[0].dev;   // step_bytes >= 64 KiB
+        unsigned long long v = 0;
+        void* args[] = {(void*)&dummy, (void*)&v};
+        ok = ok && hipLaunchKernel(kernel_set_u64(), dim3(1), dim3(64), args, 0, ln.stream) == hipSuccess;
+        ok = ok && hipStreamSynchronize(ln.stream) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -520,18 +631,25 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
     }
     Request* r = new Request;
     r->t_submit = now_s();
-    // the shape of a plain call: requests mostly run a few at a time, so a large
-    // one must be able to fill the device by itself (a batch shape caps its lanes)
-    r->plan = make_plan(p->M, p->n, p->m, p->d, p->marginals, get_shape());
+    // Requests mostly run a few at a time, so a large one must fill the device by
+    // itself (a batch shape would cap its lanes); and its queue items must be short,
+    // so that a step of step_ms still holds a few items per resident wave and a
+    // request arriving meanwhile waits at most about two steps.  Hence the plain
+    // shape with more, shorter lanes: 2^22 lanes at most, about 2^11 words each.
+    SweepShape sh = get_shape();
+    sh.p_target = std::max(sh.p_target, 22);
+    sh.p_min = std::max(sh.p_min, 18);
+    sh.c_goal = std::min(sh.c_goal, 11);
+    r->plan = make_plan(p->M, p->n, p->m, p->d, p->marginals, sh);
     if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO) {
         if (r->plan.kind == PK_SUMABS) {
             r->is_sum = true;
         } else {
-            ItemShape sh;
-            sh.item_words = S->cfg.words_per_item;
-            sh.max_items = 2048;   // large requests get larger items, not more of them
+            ItemShape ish;
+            ish.item_words = S->cfg.words_per_item;
+            ish.max_items = 1u << 16;
             std::vector<std::pair<double, Item>> its;
-            split_items(r->plan, 0, sh, its);
+            split_items(r->plan, 0, ish, its);
             std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
             for (auto& c : its) {
                 r->items.push_back(c.second);
@@ -540,6 +658,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
             }
         }
         if (align256(r->plan.blob.size()) > S->cfg.arena_bytes) r->plan.status = LD_ETOOBIG;
+        r->lane = (S->cfg.express_ms > 0 && (r->is_sum || r->remaining < S->express_cost)) ? EXPRESS : BULK;
     }
     std::lock_guard<std::mutex> g(S->mu);
     if (S->failed) {
@@ -547,7 +666,8 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         set_error(LD_EHIP);
         return LD_EHIP;
     }
-    if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO && (int)S->pending.size() >= S->cfg.max_queued) {
+    if (r->plan.status == LD_OK && r->plan.kind != PK_ZERO &&
+        (int)(S->lanes[BULK].pending.size() + S->lanes[EXPRESS].pending.size()) >= S->cfg.max_queued) {
         delete r;
         S->st_rejected++;
         set_error(LD_EBUSY);
@@ -567,7 +687,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         finish(S, r, LD_OK, 0);
         return LD_OK;
     }
-    S->pending.push_back(r);
+    S->lanes[r->lane].pending.push_back(r);
     S->cv.notify_one();
     return LD_OK;
 }
@@ -603,9 +723,10 @@ int ld_server_cancel(ld_server* S, uint64_t ticket)
     if (it == S->all.end()) return LD_ENOTFOUND;
     Request* r = it->second;
     if (r->status != LD_PENDING) return r->status;
-    auto q = std::find(S->pending.begin(), S->pending.end(), r);
-    if (q != S->pending.end()) {
-        S->pending.erase(q);
+    auto& pend = S->lanes[r->lane].pending;
+    auto q = std::find(pend.begin(), pend.end(), r);
+    if (q != pend.end()) {
+        pend.erase(q);
         finish(S, r, LD_ECANCELED, INT64_MIN);
         return LD_OK;
     }
@@ -631,7 +752,7 @@ void ld_server_stats(ld_server* S, ld_stats* out)
     out->rejected = S->st_rejected;
     out->launches = S->st_launches;
     out->items = S->st_items;
-    out->queued = (int32_t)S->pending.size();
+    out->queued = (int32_t)(S->lanes[BULK].pending.size() + S->lanes[EXPRESS].pending.size());
     for (Request* r : S->slots)
         if (r) out->inflight++;
     if (!S->latencies_ms.empty()) {
@@ -644,6 +765,7 @@ void ld_server_stats(ld_server* S, ld_stats* out)
         for (double x : v) s += x;
         out->mean_ms = s / v.size();
     }
+    if (S->wait_n) out->mean_wait_ms = S->wait_sum_ms / (double)S->wait_n;
 }
 
 void ld_server_destroy(ld_server* S)
@@ -652,11 +774,12 @@ void ld_server_destroy(ld_server* S)
     {
         std::lock_guard<std::mutex> g(S->mu);
         // queued requests are cancelled; in-flight ones finish their issued items
-        while (!S->pending.empty()) {
-            Request* r = S->pending.front();
-            S->pending.pop_front();
-            finish(S, r, LD_ECANCELED, INT64_MIN);
-        }
+        for (auto& ln : S->lanes)
+            while (!ln.pending.empty()) {
+                Request* r = ln.pending.front();
+                ln.pending.pop_front();
+                finish(S, r, LD_ECANCELED, INT64_MIN);
+            }
         for (Request* r : S->slots) {
             if (!r) continue;
             r->canceled = true;
@@ -671,7 +794,8 @@ void ld_server_destroy(ld_server* S)
     }
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
-    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    for (auto& ln : S->lanes)
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
     delete S;
 }
 

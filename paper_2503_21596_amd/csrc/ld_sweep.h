@@ -717,7 +717,30 @@ __device__ __forceinline__ int64_t wave_max(int64_t v)
 __device__ __forceinline__ void publish(int64_t* result, int64_t v)
 {
     v = wave_max(v);
-    __hip_atomic_fetch_max(result, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // through a global (not generic) pointer, so that the compiler issues the
+    // wave-uniform max from a single lane rather than one atomic per lane
+    typedef __attribute__((address_space(1))) int64_t gint64;
+    __hip_atomic_fetch_max((gint64*)(uintptr_t)result, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Serving: count one finished item of problem `prob` (its maximum already
+// published); the wave that finishes the last item reads the problem's value and
+// reports it to the host through q.done.  The decrement is issued from one lane
+// (lane 0 adds -1, the others 0) and its old value broadcast, as for queue pops.
+__device__ __forceinline__ void item_done(const QArgs& q, uint32_t prob, int64_t* result)
+{
+    typedef __attribute__((address_space(1))) uint32_t gu32;
+    typedef __attribute__((address_space(1))) int64_t gi64;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t add = (threadIdx.x & 63) == 0 ? 0xffffffffu : 0u;
+    const uint32_t old =
+        uni(__hip_atomic_fetch_add((gu32*)(uintptr_t)(q.left + prob), add, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
+    if (old == 1) {
+        const int64_t v = __hip_atomic_load((gi64*)(uintptr_t)result, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        DoneRec* d = q.done + prob;
+        __hip_atomic_store(&d->value, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&d->flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // Per-wave running maximum over consecutive items of one problem.
@@ -739,6 +762,16 @@ struct WaveBest {
     __device__ __forceinline__ void flush()
     {
         if (prob != 0xffffffffu) publish(result, best);
+    }
+    // after an item: with completion tracking (serving), publish now and count the
+    // item; otherwise keep accumulating until the problem changes
+    __device__ __forceinline__ void item_end(const QArgs& q)
+    {
+        if (q.left == nullptr) return;
+        const uint32_t p = prob;
+        flush();
+        prob = 0xffffffffu;
+        item_done(q, p, result);
     }
 };
 

@@ -68,6 +68,14 @@ struct Item {
 // `head` until it passes n_items.  With items == nullptr the items are implicit:
 // item i covers prefixes [i * per, min((i + 1) * per, n_prefix)) of problem
 // `prob` (one problem swept evenly, nothing to build or upload).
+// Completion record of one problem in host-mapped memory (serving): the wave that
+// finishes a problem's last item writes the value, then sets flag.
+struct DoneRec {
+    int64_t value;
+    uint32_t flag;
+    uint32_t pad;
+};
+
 struct QArgs {
     const Desc* descs;
     const Item* items;
@@ -76,6 +84,11 @@ struct QArgs {
     uint32_t* head;
     uint64_t per;
     uint64_t n_prefix;
+    // serving only (null otherwise): left[p] counts problem p's unfinished items;
+    // each item publishes its maximum and decrements it, and the last one reports
+    // the value in done[p]
+    uint32_t* left;
+    DoneRec* done;
 };
 
 }  // namespace ld
