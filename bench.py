@@ -64,7 +64,7 @@ def cpu_baseline(M, target_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.range_max(M, 1, 0, q, 0, 1, threads)
     t1 = time.perf_counter() - t0
-    k = max(1, min(64, int(target_s / max(t1, 1e-3))))
+    k = max(1, min(512, int(target_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     oracle.range_max(M, 1, 0, q, 1, 1 + k, threads)
     dt = time.perf_counter() - t0
