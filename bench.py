@@ -144,6 +144,42 @@ def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0)
             "offered_load_of_sequential": float(sum(durs)) / reqs[-1][0]}
 
 
+def bench_small_configs(L, synth, stream):
+    """The other workloads: 20x20 L1 (a plain call including host planning and copies,
+    median of 20, plus the kernel alone), 16x32 at d = 2, 3, 4 and 24x24 at d = 2
+    (kernel time of a prepared solve, words/s)."""
+    import numpy as np
+    out = {}
+    M = synth.config_small_l1(0)
+    L.ld_norm(M, 1, 0)
+    walls = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        L.ld_norm(M, 1, 0)
+        walls.append(time.perf_counter() - t0)
+    h = L.Prepared(M, 1, 0)
+    h.run(stream)
+    ks = []
+    for _ in range(5):
+        h.run(stream)
+        ks.append(h.kernel_ms())
+    out["l1_20x20"] = {"plain_call_ms_median": 1e3 * float(np.median(walls)), "kernel_ms": min(ks),
+                       "words": h.plan()["words"]}
+    h.close()
+    for name, A, d in [("pm16x32_d2", synth.config_pm(0), 2), ("pm16x32_d3", synth.config_pm(0), 3),
+                       ("pm16x32_d4", synth.config_pm(0), 4), ("pm24x24_d2", synth.config_pm24(0), 2)]:
+        h = L.Prepared(A, d, 0)
+        v = h.run(stream)
+        ks = []
+        for _ in range(3):
+            h.run(stream)
+            ks.append(h.kernel_ms())
+        w = h.plan()["words"]
+        out[name] = {"value": v, "kernel_ms": min(ks), "words": w, "words_per_s": w / (min(ks) / 1e3)}
+        h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +279,8 @@ def main():
                           "steps_per_s": hm.plan()["words"] / (hm.kernel_ms() / 1e3),
                           "matches_oracle": (vm == gm) if gm is not None else None}
         hm.close()
+        print("bench: small configs", file=sys.stderr, flush=True)
+        out["other_configs"] = bench_small_configs(L, synth, stream)
         print("bench: argmax", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         va, av, bv = L.ld_argmax(M, 1, 0)

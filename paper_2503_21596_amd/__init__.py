@@ -69,7 +69,7 @@ SIGNATURES = {
     "ld_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
     "ld_gray_digit": (_U32, [_U32, _U32, _U64]),
     "ld_gray_change": (_I32, [_U32, _U64, _P, _P]),
-    "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32, _I32]),
+    "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32, _I32, _I32]),
     "ld_prepare": (_P, [_P, _I32, _I32, _I32, _I32]),
     "ld_run": (ctypes.c_int, [_P, _P, _P]),
     "ld_last_kernel_ms": (ctypes.c_float, [_P]),
@@ -286,8 +286,8 @@ def gray_change(d: int, j: int):
 
 
 def set_sweep_shape(p_target: int = 0, c_min: int = 0, r_drop: int = -1, dary_ptab: int = 0,
-                    sgpr_r: int = -1) -> None:
-    lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab, sgpr_r)
+                    sgpr_r: int = -1, dary_sgpr: int = -1) -> None:
+    lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab, sgpr_r, dary_sgpr)
 
 
 def autotune(path: Optional[str] = None, budget_seconds: float = 20.0) -> None:

@@ -24,6 +24,7 @@ UNITS = [
     ("ld_kernels_bin.hip", ["-DLD_KIND=1"], "kbin1.o"),
     ("ld_kernels_bin.hip", ["-DLD_KIND=2"], "kbin2.o"),
     ("ld_kernels_dary.hip", [], "kdary.o"),
+    ("ld_kernels_dary_s.hip", [], "kdarys.o"),
     ("ld_plan.cpp", [], "plan.o"),
     ("ld_program.cpp", [], "program.o"),
     ("ld_api.cpp", [], "api.o"),

@@ -306,7 +306,8 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to)
     return (int32_t)i;
 }
 
-void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r)
+void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r,
+                        int32_t dary_sgpr)
 {
     SweepShape s = get_shape();
     if (p_target > 0) s.p_target = std::min(p_target, 40);
@@ -314,6 +315,7 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
     if (r_drop >= 0) s.r_drop = r_drop ? 1 : 0;
     if (dary_ptab > 0) s.dary_ptab = std::min(dary_ptab, 16);
     if (sgpr_r >= 0) s.sgpr_r = std::min(sgpr_r, MAX_RS);
+    if (dary_sgpr >= 0) s.dary_sgpr = dary_sgpr ? 1 : 0;
     set_shape(s);
 }
 

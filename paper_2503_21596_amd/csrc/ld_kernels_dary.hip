@@ -4,7 +4,7 @@
 
 #include "ld_registry.h"
 #include "ld_program.h"
-#include "ld_sweep.h"
+#include "ld_sweep_dary.h"
 
 namespace ld {
 

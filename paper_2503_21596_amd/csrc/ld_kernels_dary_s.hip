@@ -1,0 +1,72 @@
+// d-ary sweep kernels with the subset operands streamed through SGPRs (Dary32S),
+// for d = 3, 4; a compilation unit of their own so that the build runs in parallel.
+#include <hip/hip_runtime.h>
+#include <utility>
+
+#include "ld_registry.h"
+#include "ld_sweep_dary.h"
+
+namespace ld {
+
+// Persistent queue kernel (see k_bin32): one item = a range of prefixes of one
+// problem, one lane per prefix.
+template <int MP, int DD>
+__global__ __launch_bounds__(256) void k_dary32s(QArgs q)
+{
+    using K = Dary32S<MP, DD, DARY_RS>;
+    const uint32_t lane = threadIdx.x & 63;
+    WaveBest wb;
+    Item it;
+    while (next_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
+        uint32_t best = 0;
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            uint32_t pb = 0;
+            K::prefix(D, D.pfx_base + it.p0 + i, pb);
+            best = max(best, pb);
+            if (D.rec) D.rec[it.p0 + i] = (int64_t)pb;
+        }
+        wb.add((int64_t)best);
+        wb.item_end(q);
+    }
+    wb.flush();
+}
+
+namespace {
+
+constexpr int NMPD = MAX_MP / 4;   // mp = 4, 8, ..., 64
+const void* g_dary32s[MAX_D + 1][NMPD] = {};
+
+template <int DD, int MP>
+void reg_one()
+{
+    if constexpr (dary_s_fits(MP, DD)) g_dary32s[DD][MP / 4 - 1] = (const void*)&k_dary32s<MP, DD>;
+}
+
+template <int DD, int... I>
+void reg_mps(std::integer_sequence<int, I...>)
+{
+    (reg_one<DD, 4 * (I + 1)>(), ...);
+}
+
+struct Init {
+    Init()
+    {
+        reg_mps<3>(std::make_integer_sequence<int, NMPD>{});
+        reg_mps<4>(std::make_integer_sequence<int, NMPD>{});
+    }
+} g_init;
+
+}  // namespace
+
+const void* kernel_dary32s(int d, int mp)
+{
+    if (d < 0 || d > MAX_D || mp < 4 || mp > MAX_MP || (mp & 3)) return nullptr;
+    return g_dary32s[d][mp / 4 - 1];
+}
+
+}  // namespace ld

@@ -321,7 +321,8 @@ void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fi
     p.off_hid = align256(es * (size_t)mp);
     p.off_mid = align256(p.off_hid + es * (size_t)std::max(nh, 1) * mp);
     p.off_offs = align256(p.off_mid + es * (size_t)std::max(C, 1) * mp);
-    p.off_tab = align256(p.off_offs + 4 * (size_t)NS * mp);
+    const int RS = (mp + 15) & ~15;   // subset-operand row stride (scalar loads of 8 dwords)
+    p.off_tab = align256(p.off_offs + 4 * (size_t)NS * RS);
     const size_t end = align256(p.off_tab + 8 * std::max<size_t>(tab.size(), 1));
     p.blob.assign(end, 0);
     for (int y = 0; y < mp; ++y) {
@@ -348,7 +349,7 @@ void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fi
             if (y < m)
                 for (int i = 0; i < R; ++i)
                     if ((sub >> i) & 1) low += A.at(low0 + i, y);
-            put<uint32_t>(p.blob, p.off_offs, (size_t)sub * mp + y, (uint32_t)(BIAS - low));
+            put<uint32_t>(p.blob, p.off_offs, (size_t)sub * RS + y, (uint32_t)(BIAS - low));
         }
     for (size_t i = 0; i < tab.size(); ++i) put<uint64_t>(p.blob, p.off_tab, i, tab[i]);
 }
@@ -586,14 +587,20 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     // d >= 3, d < n
     p.mp = pad_dary(A.m);
     p.kernel = nullptr;
-    if (A.m <= MAX_MP && d <= MAX_D)
-        p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
-    if (!p.kernel && !use_wide(p, d)) {
-        p.status = LD_ETOOBIG;
-        return p;
+    if (A.m <= MAX_MP && d <= MAX_D && !p.i64 && sh.dary_sgpr && A.n >= 1 + DARY_RS) {
+        p.kernel = kernel_dary32s(d, p.mp);
+        if (p.kernel) p.R = DARY_RS;
     }
-    // the register kernel scores R low rows per state; the others walk every row
-    p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    if (!p.kernel) {
+        if (A.m <= MAX_MP && d <= MAX_D)
+            p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
+        if (!p.kernel && !use_wide(p, d)) {
+            p.status = LD_ETOOBIG;
+            return p;
+        }
+        // the register kernel scores R low rows per state; the others walk every row
+        p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    }
     // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
     // row is fixed (message 0), which is the paper's fix-one-entry reduction
     p.P_tab = d <= 16 ? std::min(A.n - p.R, std::max(1, std::min(16, sh.dary_ptab))) : 1;
@@ -722,12 +729,18 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
     // d >= 3: row 0 fixed at message 0; rows 1..n-q-1 mid; the last q rows prefix
     p.mp = pad_dary(m);
     p.kernel = nullptr;
-    if (m <= MAX_MP && d <= MAX_D) p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
-    if (!p.kernel && !use_wide(p, d)) {
-        p.status = LD_ETOOBIG;
-        return p;
+    if (m <= MAX_MP && d <= MAX_D && !p.i64 && get_shape().dary_sgpr) {
+        p.kernel = kernel_dary32s(d, p.mp);
+        if (p.kernel) p.R = DARY_RS;
     }
-    p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    if (!p.kernel) {
+        if (m <= MAX_MP && d <= MAX_D) p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
+        if (!p.kernel && !use_wide(p, d)) {
+            p.status = LD_ETOOBIG;
+            return p;
+        }
+        p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    }
     // rows 1..n-q-1 give the C mid rows and the R low rows (zero rows pad them when
     // there are fewer than R: a zero row changes no message sum)
     const int lowmid = std::max(free_rows, p.R);

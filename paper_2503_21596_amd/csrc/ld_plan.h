@@ -28,6 +28,7 @@ struct SweepShape {
                                // lanes exist (0: keep dary_cwords words per lane)
     int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel
+    int dary_sgpr = 1;         // 1: d-ary int32 problems use the SGPR-operand kernel where built
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)
     int pfx_cap = 0;           // > 0 (batch planning): at most about 2^pfx_cap prefixes per

@@ -29,6 +29,11 @@ constexpr int bin_rmax(int mp, int kind)
 // d-ary: d vectors of mp columns
 constexpr bool dary_fits(int mp, int d) { return d * mp <= 192; }
 
+// SGPR-operand d-ary kernels: R = 3 low rows, built for d = 3, 4 while the d
+// message vectors take at most 160 VGPRs
+constexpr int DARY_RS = 3;
+constexpr bool dary_s_fits(int mp, int d) { return (d == 3 || d == 4) && d * mp <= 160; }
+
 // d-ary low rows scored per state: the largest R <= 2 whose 2^R - 1 subset
 // operands fit beside the d state vectors, (d + 2^R - 1) * mp <= 200
 constexpr int dary_r(int mp, int d)
@@ -47,6 +52,7 @@ const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin32s(int kind, int mp, int R);
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
+const void* kernel_dary32s(int d, int mp);   // SGPR-operand d-ary kernel (DARY_RS low rows)
 const void* kernel_dary64(int d, int mp);
 const void* kernel_sumabs_many();
 const void* kernel_wide();

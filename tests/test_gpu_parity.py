@@ -147,11 +147,11 @@ def test_sweep_shapes_agree():
     try:
         for p_target, c_min, r_drop, sgpr_r in [(20, 4, 0, 4), (6, 10, 0, 5), (12, 1, 1, 0), (3, 4, 1, 0),
                                                 (3, 4, 0, 4)]:
-            L.set_sweep_shape(p_target, c_min, r_drop, 8, sgpr_r)
+            L.set_sweep_shape(p_target, c_min, r_drop, 8, sgpr_r, -1)
             assert L.ld_norm(M, 1, 0) == want
             assert L.ld_norm(M, 1, 1) == oracle.lmarg(M)
     finally:
-        L.set_sweep_shape(20, 4, 0, 8, 5)
+        L.set_sweep_shape(20, 4, 0, 8, 5, -1)
 
 
 def planted(seed, n, m):
@@ -179,6 +179,25 @@ def test_reductions_planted(d, marg):
         check(M, d, marg)
 
 
+@pytest.mark.parametrize("dary_sgpr", [0, 1])
+def test_dary_kernel_variants(dary_sgpr):
+    """Both int32 d-ary kernels (subset operands in VGPRs with up to two low rows,
+    or streamed through SGPRs with three) against the oracle, d = 3, 4, every
+    column count up to the SGPR kernel's limit and row counts around R + 1."""
+    say("dary variants", dary_sgpr)
+    try:
+        L.set_sweep_shape(0, 0, -1, 0, -1, dary_sgpr)
+        for i, (n, m, d) in enumerate([(4, 5, 3), (5, 8, 3), (7, 13, 3), (9, 32, 3), (10, 52, 3), (8, 3, 3),
+                                       (5, 6, 4), (7, 17, 4), (8, 40, 4), (9, 24, 4), (6, 1, 4)]):
+            M = synth.matrix(950 + i, n, m, -500, 500, "dvariants")
+            p = L.plan(M, d, 0)
+            if dary_sgpr and p["kind_name"] == "L_d" and p["i64"] == 0 and p["mp"] * d <= 160:
+                assert p["R"] == 3, p
+            check(M, d, 0)
+    finally:
+        L.set_sweep_shape(0, 0, -1, 0, -1, 1)
+
+
 @pytest.mark.parametrize("sgpr_r", [0, 4, 5])
 def test_binary_kernel_variants(sgpr_r):
     """Both int32 binary kernels (low-row operands in VGPRs, or streamed through
@@ -187,7 +206,7 @@ def test_binary_kernel_variants(sgpr_r):
     and row counts below, at and above the low-row count."""
     say("binary variants", sgpr_r)
     try:
-        L.set_sweep_shape(0, 0, -1, 0, sgpr_r)
+        L.set_sweep_shape(0, 0, -1, 0, sgpr_r, -1)
         cases = [(n, m) for n, m in [(1, 5), (2, 3), (3, 8), (4, 1), (5, 17), (6, 64), (7, 63), (9, 42),
                                      (12, 9), (13, 33), (14, 50), (15, 2), (16, 24), (11, 57)]]
         for i, (n, m) in enumerate(cases):
@@ -198,7 +217,7 @@ def test_binary_kernel_variants(sgpr_r):
                     assert p["R"] == sgpr_r, p
                 check(M, d, marg)
     finally:
-        L.set_sweep_shape(0, 0, -1, 0, 5)
+        L.set_sweep_shape(0, 0, -1, 0, 5, -1)
 
 
 # ---------------------------------------------------------------------------

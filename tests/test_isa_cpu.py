@@ -78,7 +78,7 @@ def test_scan_catches_a_redirected_load():
     assert scan(ok) == []
 
 
-@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o"])
+@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o", "kdarys.o"])
 def test_scalar_loads_keep_their_address(obj, tmp_path):
     path = os.path.join(BUILD, obj)
     if not os.path.exists(path):
