@@ -93,6 +93,19 @@ void ld_batch_release(ld_batch* b);
 int64_t ld_norm_range(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
                       int32_t q, uint64_t prefix_begin, uint64_t prefix_end);
 
+/* ld_norm_resumable -- a long solve that survives interruption (a multi-hour
+ * d = 3 problem, a preemptible job).  The search space of ld_norm's plan is swept
+ * in chunks of about chunk_seconds; after every chunk the best value so far and
+ * the next prefix are written to state_path (a text file, replaced atomically
+ * through state_path + ".tmp").  If state_path holds the state of the same matrix,
+ * kind and plan, the sweep continues where it stopped; any other content is
+ * overwritten and the sweep starts over.  Returns LD_OK with *value once the whole
+ * space has been swept (the value equals ld_norm's), or LD_PENDING when
+ * max_seconds have passed (the state is saved: call again to continue), or an
+ * error code (LD_EINVAL also when the state file cannot be written). */
+int ld_norm_resumable(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
+                      const char* state_path, double chunk_seconds, double max_seconds, int64_t* value);
+
 /* ld_argmax -- the value together with one assignment that reaches it (the
  * strategy the paper's program reports next to the value, Sec. 2.1.3).
  * assignment (n entries, caller-owned): d = 1: a_x in {-1, +1} for every row

@@ -64,6 +64,8 @@ SIGNATURES = {
     "ld_norm_batch": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "ld_norm_range": (_I64, [_P, _I32, _I32, _I32, _I32, _I32, _U64, _U64]),
     "ld_argmax": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _P]),
+    "ld_norm_resumable": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, ctypes.c_char_p, ctypes.c_double,
+                                         ctypes.c_double, _P]),
     "ld_last_error": (ctypes.c_int, []),
     "ld_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ld_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
@@ -167,6 +169,22 @@ def ld_argmax(M, d: int = 1, marginals: int = 0):
     if rc != LD_OK:
         raise _err(rc)
     return int(v[0]), rows, (cols if d == 1 else None)
+
+
+def ld_norm_resumable(M, d: int, marginals: int, state_path: str, chunk_seconds: float = 10.0,
+                      max_seconds: float = float("inf")):
+    """The value once the whole search space has been swept (possibly over several
+    calls), or None when max_seconds ran out first; progress is kept in state_path."""
+    a = _mat(M)
+    v = np.zeros(1, dtype=np.int64)
+    ms = float(max_seconds) if max_seconds != float("inf") else 1e300
+    rc = lib().ld_norm_resumable(a.ctypes.data, a.shape[0], a.shape[1], int(d), int(marginals),
+                                 os.fsencode(state_path), float(chunk_seconds), ms, v.ctypes.data)
+    if rc == LD_PENDING:
+        return None
+    if rc != LD_OK:
+        raise _err(rc)
+    return int(v[0])
 
 
 def ld_norm_batch(problems: Sequence[Tuple], stream=None, return_status: bool = False):

@@ -32,6 +32,7 @@ UNITS = [
     ("ld_server.cpp", [], "server.o"),
     ("ld_tune.cpp", [], "tune.o"),
     ("ld_argmax.cpp", [], "argmax.o"),
+    ("ld_resume.cpp", [], "resume.o"),
 ]
 
 
