@@ -92,3 +92,25 @@ def test_prepared_single_runs_repeat():
     for _ in range(4):
         assert h.run() == want
     h.close()
+
+
+def test_full_batch_sampled_against_oracle():
+    """The 4096-problem batch workload exactly as the benchmark runs it (one device
+    program, graph replay): every value equals the plain call's, and a seeded sample
+    of the problems small enough for the oracle equals the oracle's value."""
+    say("full batch sampled")
+    probs = synth.batch_problems(0, 4096)
+    B = L.Batch(probs)
+    got = B.run()
+    again = B.run()
+    B.close()
+    assert list(got) == list(again)
+    cheap = [i for i, (M, d, marg) in enumerate(probs)
+             if (d <= 2 and M.shape[0] <= 17) or (d == 3 and M.shape[0] <= 12)]
+    key = synth.stream_key(11, "batch_sample")
+    pick = sorted({cheap[int(r) % len(cheap)] for r in synth.uniform_ints(key, 80, 0, 1 << 30)})
+    for i in pick:
+        M, d, marg = probs[i]
+        assert got[i] == oracle.norm(M, d, marg), (i, M.shape, d, marg)
+    plain = [L.ld_norm(M, d, marg) for M, d, marg in probs[:512]]
+    assert list(got[:512]) == plain
