@@ -456,7 +456,9 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         const uint32_t resident = resident_blocks(g.first.first, threads, lds);
         const uint32_t per_cu = S->cus > 0 ? resident / (uint32_t)S->cus : 0;
         uint32_t cap = resident;
-        if (li == EXPRESS) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
+        // express work takes one block per CU while bulk steps run, the whole
+        // device otherwise
+        if (li == EXPRESS && busy_steps(S->lanes[BULK]) > 0) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
         else if (per_cu >= 3) cap = resident - (uint32_t)S->cus;   // one block per CU for express work
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, cap));
         void* args[] = {(void*)&q};
