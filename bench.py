@@ -207,6 +207,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", default="", help="load this autotuner table before measuring")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
                          "known traffic, to scale the HBM counters of a profiler run)")
@@ -225,6 +226,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.tuning:
+        L.load_tuning(a.tuning)
     M = synth.config_42_l1(0)
     h = L.Prepared(M, 1, 0)
     plan = h.plan()

@@ -223,7 +223,8 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
  * int32 binary kernel that reads its low-row operands from SGPRs (4 or 5), or 0
  * for the kernel that holds them in VGPRs; dary_sgpr: 1 for the d-ary kernel with
  * SGPR operands (d = 3, 4, three low rows) where it is built, 0 for the VGPR one.
- * Values never depend on the shape. */
+ * An explicit sgpr_r or dary_sgpr also replaces the autotuner's per-width choices
+ * for those kinds.  Values never depend on the shape. */
 void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r,
                         int32_t dary_sgpr);
 

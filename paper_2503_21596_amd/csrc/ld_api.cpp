@@ -314,8 +314,17 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
     if (c_min > 0) s.c_min = std::min(c_min, 31);
     if (r_drop >= 0) s.r_drop = r_drop ? 1 : 0;
     if (dary_ptab > 0) s.dary_ptab = std::min(dary_ptab, 16);
-    if (sgpr_r >= 0) s.sgpr_r = std::min(sgpr_r, MAX_RS);
-    if (dary_sgpr >= 0) s.dary_sgpr = dary_sgpr ? 1 : 0;
+    // an explicit variant replaces the tuned per-width choices of its kinds
+    if (sgpr_r >= 0) {
+        s.sgpr_r = std::min(sgpr_r, MAX_RS);
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 4; ++b) s.variant[c][b] = -1;
+    }
+    if (dary_sgpr >= 0) {
+        s.dary_sgpr = dary_sgpr ? 1 : 0;
+        for (int c = 2; c < 4; ++c)
+            for (int b = 0; b < 4; ++b) s.variant[c][b] = -1;
+    }
     set_shape(s);
 }
 

@@ -451,11 +451,21 @@ bool use_wide(Plan& p, int states)
 // int32 binary kernel: the SGPR-operand kernel with sh.sgpr_r low rows when it
 // exists for this width, else the VGPR-operand kernel with as many low rows as
 // its register budget allows
+bool dary_sgpr_for(const SweepShape& sh, int d, int mp)
+{
+    const int cls = variant_class(PK_LD, d);
+    const int tuned = cls >= 0 ? sh.variant[cls][variant_bucket(mp)] : -1;
+    return (tuned >= 0 ? tuned : sh.dary_sgpr) != 0;
+}
+
 void pick_bin32(Plan& p, const SweepShape& sh)
 {
-    p.kernel = sh.sgpr_r > 0 ? kernel_bin32s(p.kind, p.mp, sh.sgpr_r) : nullptr;
+    const int cls = variant_class(p.kind, p.d);
+    const int tuned = cls >= 0 ? sh.variant[cls][variant_bucket(p.mp)] : -1;
+    const int sr = tuned >= 0 ? tuned : sh.sgpr_r;
+    p.kernel = sr > 0 ? kernel_bin32s(p.kind, p.mp, sr) : nullptr;
     if (p.kernel) {
-        p.R = sh.sgpr_r;
+        p.R = sr;
         return;
     }
     p.R = std::max(0, bin_rmax(p.mp, p.kind) - (sh.r_drop ? 1 : 0));
@@ -503,6 +513,17 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
 }
 
 }  // namespace
+
+int variant_class(int kind, int d)
+{
+    switch (kind) {
+    case PK_L1:
+    case PK_MARG: return 0;
+    case PK_L2: return 1;
+    case PK_LD: return d == 3 ? 2 : d == 4 ? 3 : -1;
+    default: return -1;
+    }
+}
 
 SweepShape get_shape()
 {
@@ -587,7 +608,7 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     // d >= 3, d < n
     p.mp = pad_dary(A.m);
     p.kernel = nullptr;
-    if (A.m <= MAX_MP && d <= MAX_D && !p.i64 && sh.dary_sgpr && A.n >= 1 + DARY_RS) {
+    if (A.m <= MAX_MP && d <= MAX_D && !p.i64 && dary_sgpr_for(sh, d, p.mp) && A.n >= 1 + DARY_RS) {
         p.kernel = kernel_dary32s(d, p.mp);
         if (p.kernel) p.R = DARY_RS;
     }
@@ -729,7 +750,7 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
     // d >= 3: row 0 fixed at message 0; rows 1..n-q-1 mid; the last q rows prefix
     p.mp = pad_dary(m);
     p.kernel = nullptr;
-    if (m <= MAX_MP && d <= MAX_D && !p.i64 && get_shape().dary_sgpr) {
+    if (m <= MAX_MP && d <= MAX_D && !p.i64 && dary_sgpr_for(get_shape(), d, p.mp)) {
         p.kernel = kernel_dary32s(d, p.mp);
         if (p.kernel) p.R = DARY_RS;
     }

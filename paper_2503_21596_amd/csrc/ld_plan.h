@@ -16,8 +16,8 @@ using Members = std::vector<std::pair<int, int>>;
 
 struct SweepShape {
     int p_target = 20;   // at most this many high rows (2^20 lanes) for a binary problem
-    int p_min = 16;      // at least this many, when the problem has them
-    int c_goal = 14;     // between the two: aim for 2^c_goal words per prefix
+    int p_min = 19;      // at least this many, when the problem has them
+    int c_goal = 12;     // between the two: aim for 2^c_goal words per prefix
     int c_min = 4;       // least mid rows per lane when the problem allows it
     int r_drop = 0;      // 1: one low row fewer than the register budget allows
     int dary_ptab = 8;   // restricted-growth prefix rows for d >= 3
@@ -29,6 +29,10 @@ struct SweepShape {
     int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel
     int dary_sgpr = 1;         // 1: d-ary int32 problems use the SGPR-operand kernel where built
+    // tuned kernel variant per (kind class, padded-width bucket); -1 = the setting
+    // above.  Classes: 0 L1 / L_marg, 1 L2, 2 L_3, 3 L_4; buckets: mp in (16b, 16b + 16].
+    // Binary classes hold sgpr_r (0, 4, 5), d-ary classes dary_sgpr (0, 1).
+    int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)
     int pfx_cap = 0;           // > 0 (batch planning): at most about 2^pfx_cap prefixes per
@@ -59,6 +63,10 @@ struct Plan {
     int wide = 0;                  // 1: the wide (LDS-state, one wave per prefix) kernel
     size_t lds = 0;                // dynamic LDS bytes of the wide kernel
 };
+
+// class and bucket of SweepShape::variant for a problem (class -1: none)
+int variant_class(int kind, int d);
+inline int variant_bucket(int mp) { return mp <= 16 ? 0 : mp <= 32 ? 1 : mp <= 48 ? 2 : 3; }
 
 SweepShape get_shape();
 void set_shape(const SweepShape& s);

@@ -74,7 +74,6 @@ struct Request {
     size_t next = 0;                 // first item not yet issued
     double remaining = 0;            // estimated cost of the items not yet issued
     uint32_t outstanding = 0;        // issued items whose step has not retired
-    bool uploaded = false;
     bool canceled = false;
     bool is_sum = false;
     int lane = 0;                    // 0 bulk, 1 express
@@ -260,6 +259,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     const int max_slots = S->cfg.max_inflight_problems;
     std::vector<Request*> admitted;
     std::vector<std::pair<Request*, std::vector<Item>>> picks;
+    bool express_active = false;
     {
         std::lock_guard<std::mutex> g(S->mu);
         // 2. admission by slot and arena space (FIFO; a request too big for the
@@ -282,7 +282,14 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         for (Request* r : S->slots)
             if (r && r->lane == li && r->next < r->items.size()) live.push_back(r);
         std::sort(live.begin(), live.end(), [](Request* a, Request* b) { return a->remaining < b->remaining; });
-        const double budget = COST_UNITS_PER_S * S->cfg.step_ms * 1e-3;
+        // a long bulk queue (saturation) gets steps twice as long: fewer steps, less
+        // per-step overhead; the express lane keeps small requests responsive
+        double budget = COST_UNITS_PER_S * S->cfg.step_ms * 1e-3;
+        if (li == BULK && live.size() > 16) budget *= 2;
+        // bulk launches leave room for express work only while there is some
+        express_active = busy_steps(S->lanes[EXPRESS]) > 0 || !S->lanes[EXPRESS].pending.empty();
+        for (Request* r : S->slots)
+            if (r && r->lane == EXPRESS && r->status == LD_PENDING) express_active = true;
         double used = 0;
         size_t n_items = 0;
         for (Request* r : live) {
@@ -457,9 +464,12 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         const uint32_t per_cu = S->cus > 0 ? resident / (uint32_t)S->cus : 0;
         uint32_t cap = resident;
         // express work takes one block per CU while bulk steps run, the whole
-        // device otherwise
-        if (li == EXPRESS && busy_steps(S->lanes[BULK]) > 0) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
-        else if (per_cu >= 3) cap = resident - (uint32_t)S->cus;   // one block per CU for express work
+        // device otherwise; bulk work leaves one block per CU to it while it has any
+        if (li == EXPRESS) {
+            if (busy_steps(S->lanes[BULK]) > 0) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
+        } else if (per_cu >= 3 && express_active) {
+            cap = resident - (uint32_t)S->cus;
+        }
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, cap));
         void* args[] = {(void*)&q};
         ok = ok && hipLaunchKernel(g.first.first, dim3(blocks), dim3(threads), args, lds, s) == hipSuccess;

@@ -94,12 +94,18 @@ double time_plain(const std::vector<int32_t>& M, int n, int m)
     return best;
 }
 
+const char* const CLASS_NAME[4] = {"l1", "l2", "d3", "d4"};
+
 bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
 {
     FILE* f = std::fopen(path, "w");
     if (!f) return false;
+    std::fprintf(f, "{\n");
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            std::fprintf(f, "  \"variant_%s_%d\": %d,\n", CLASS_NAME[c], b, t.variant[c][b]);
     std::fprintf(f,
-                 "{\n  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
+                 "  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
                  "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"plain_p_min\": %d,\n  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
@@ -138,6 +144,7 @@ void set_tuning(const Tuning& t)
     s.c_goal = t.plain_c_goal;
     s.r_drop = t.plain_r_drop;
     s.sgpr_r = t.sgpr_r;
+    std::memcpy(s.variant, t.variant, sizeof s.variant);
     set_shape(s);
 }
 
@@ -242,6 +249,49 @@ int ld_autotune(const char* path, double budget_seconds)
         best = bp;
     }
     set_tuning(best);
+
+    // kernel variant per kind class and width bucket, timed on one problem each of
+    // a few milliseconds (L1 with 33 rows, L2 with 32, L_3 with 19, L_4 with 15;
+    // width 16b + 14, or square for the narrowest L1 bucket so that the planner
+    // does not transpose it)
+    {
+        Rng r{0x7a2};
+        const int rows[4] = {33, 32, 19, 15};
+        const int dval[4] = {1, 2, 3, 4};
+        for (int c = 0; c < 4 && now_s() < t_end; ++c)
+            for (int b = 0; b < 4 && now_s() < t_end; ++b) {
+                const int m = 16 * b + 14;
+                const int n = (c == 0) ? std::min(rows[c], m) : rows[c];
+                std::vector<int32_t> M((size_t)n * m);
+                for (auto& x : M) x = r.uniform(-100, 100);
+                std::vector<int> options = c < 2 ? std::vector<int>{5, 4, 0} : std::vector<int>{1, 0};
+                double bt = 1e30;
+                int pick = -1;
+                for (int o : options) {
+                    Tuning t = best;
+                    t.variant[c][b] = o;
+                    set_tuning(t);
+                    double dt = 1e30;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        const double t0 = now_s();
+                        if (ld_norm(M.data(), n, m, dval[c], 0) == INT64_MIN) {
+                            dt = 1e30;
+                            break;
+                        }
+                        dt = std::min(dt, now_s() - t0);
+                    }
+                    std::snprintf(buf, sizeof buf, ", {\"class\": \"%s\", \"bucket\": %d, \"variant\": %d, \"ms\": %.3f}",
+                                  CLASS_NAME[c], b, o, 1e3 * dt);
+                    notes += buf;
+                    if (dt < bt) {
+                        bt = dt;
+                        pick = o;
+                    }
+                }
+                best.variant[c][b] = pick;
+            }
+    }
+    set_tuning(best);
     if (path && *path && !write_tuning(path, best, notes)) {
         set_error(LD_EINVAL);
         return LD_EINVAL;
@@ -272,6 +322,12 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "plain_c_goal", &v)) t.plain_c_goal = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
     if (read_key(text, "sgpr_r", &v)) t.sgpr_r = (v == 4 || v == 5) ? (int)v : 0;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b) {
+            char key[32];
+            std::snprintf(key, sizeof key, "variant_%s_%d", CLASS_NAME[c], b);
+            if (read_key(text, key, &v)) t.variant[c][b] = (int)v;
+        }
     set_tuning(t);
     return LD_OK;
 }

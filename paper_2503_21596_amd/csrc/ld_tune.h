@@ -6,15 +6,17 @@
 namespace ld {
 
 struct Tuning {
-    int bin_c_target = 10;        // batch, binary kinds: mid + low rows per prefix (2^c words)
-    int dary_cwords = 2187;       // batch, d >= 3: words per prefix (d^C <= this)
-    double item_words = 1 << 18;  // batch: words per queue item
+    int bin_c_target = 8;         // batch, binary kinds: mid + low rows per prefix (2^c words)
+    int dary_cwords = 729;        // batch, d >= 3: words per prefix (d^C <= this)
+    double item_words = 1 << 16;  // batch: words per queue item
     int batch_pfx_cap = 0;        // batch: at most about 2^this prefixes per problem (0: no cap)
     int plain_p_target = 20;      // plain calls: at most 2^this lanes for a binary problem
-    int plain_p_min = 16;         // plain calls: at least 2^this lanes when the problem has them
-    int plain_c_goal = 14;        // plain calls: aim for 2^this words per prefix
+    int plain_p_min = 19;         // plain calls: at least 2^this lanes when the problem has them
+    int plain_c_goal = 12;        // plain calls: aim for 2^this words per prefix
     int plain_r_drop = 0;         // plain calls: one low row fewer than the register budget allows
     int sgpr_r = 5;               // int32 binary kinds: low rows of the SGPR-operand kernel (0: VGPR kernel)
+    // kernel variant per (kind class, width bucket), as SweepShape::variant (-1: the above)
+    int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
 };
 
 Tuning get_tuning();

@@ -200,3 +200,22 @@ def test_gray_hamming_one(d):
         cur = [L.gray_digit(d, k, j) for k in range(5)]
         diff = [k for k in range(5) if prev[k] != cur[k]]
         assert diff == [i] and prev[i] == f and cur[i] == t
+
+
+def test_tuning_file_round_trip(tmp_path):
+    """ld_load_tuning reads the autotuner's JSON (host only) and new plans follow
+    it; a missing file is an error.  The shipped table is restored afterwards."""
+    path = tmp_path / "t.json"
+    path.write_text('{"bin_c_target": 10, "plain_p_target": 18, "plain_p_min": 12, "plain_c_goal": 14, '
+                    '"sgpr_r": 4, "variant_l1_2": -1, "measured": []}')
+    M = synth.config_42_l1(0)
+    try:
+        L.load_tuning(str(path))
+        p = L.plan(M, 1, 0)
+        assert p["P"] == 18 and p["R"] == 4 and p["words"] == 2.0 ** 41
+        with pytest.raises(L.LdError):
+            L.load_tuning(str(tmp_path / "missing.json"))
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+    p = L.plan(M, 1, 0)
+    assert p["R"] == 5 and p["P"] == 20

@@ -331,3 +331,21 @@ def test_batch_matches_plain():
     out = L.ld_norm_batch(probs)
     for (M, d, marg), v in zip(probs, out):
         assert v == oracle.norm(M, d, marg)
+
+
+def test_autotune_writes_table_and_keeps_values(tmp_path):
+    """A short autotuner run writes its table; whatever it picks, values stay equal."""
+    say("autotune")
+    probs = [(synth.matrix(990 + i, 10 + i % 7, 12 + i % 9, -99, 99, "tune"), 1 + i % 3, 0) for i in range(12)]
+    before = [L.ld_norm(M, d, marg) for M, d, marg in probs]
+    path = str(tmp_path / "tuning.json")
+    try:
+        L.autotune(path, 2.0)
+        table = json.load(open(path))
+        for key in ("bin_c_target", "dary_cwords", "item_words", "plain_p_target", "plain_c_goal", "sgpr_r",
+                    "measured"):
+            assert key in table, key
+        assert len(table["measured"]) >= 1
+        assert [L.ld_norm(M, d, marg) for M, d, marg in probs] == before
+    finally:
+        L.load_tuning(L.TUNING_PATH)
