@@ -172,7 +172,7 @@ typedef struct {
     int32_t max_queued;             /* submitted but not admitted; beyond: LD_EBUSY (0: 65536) */
     int32_t device;                 /* HIP device index                                     */
     double express_ms;              /* requests below this estimated device time take the
-                                       express lane (0: 0.25 ms; negative: no express lane) */
+                                       express lane (0: 1 ms; negative: no express lane)    */
 } ld_server_config;
 
 typedef struct {
