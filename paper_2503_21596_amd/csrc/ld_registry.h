@@ -43,10 +43,6 @@ constexpr int dary_r(int mp, int d)
     return 0;
 }
 
-struct KernelRef {
-    const void* fn = nullptr;   // __global__ function
-};
-
 // lookups; return nullptr when no instantiation exists
 const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin32s(int kind, int mp, int R);

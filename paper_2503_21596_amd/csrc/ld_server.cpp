@@ -386,27 +386,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         Request* r = admitted[k];
         std::memcpy(H + blob_at[k], r->plan.blob.data(), r->plan.blob.size());
         ops.push_back({D + blob_at[k], S->arena_dev + r->arena_off, (uint64_t)r->plan.blob.size()});
-        const Plan& p = r->plan;
-        const uint8_t* base = S->arena_dev + r->arena_off;
-        Desc d{};
-        d.kind = p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
-        d.m = p.m;
-        d.mp = p.mp;
-        d.d = p.d;
-        d.i64 = p.i64;
-        d.R = p.R;
-        d.C = p.C;
-        d.P = p.P;
-        d.P_tab = p.P_tab;
-        d.pfx_base = p.pfx_base;
-        d.n_prefix = p.n_prefix;
-        d.dpow_free = p.dpow_free;
-        d.base = base + p.off_base;
-        d.hid = base + p.off_hid;
-        d.mid = base + p.off_mid;
-        d.offs = base + p.off_offs;
-        d.tab = (const uint64_t*)(base + p.off_tab);
-        d.result = S->d_results + r->slot;
+        const Desc d = make_desc(r->plan, S->arena_dev + r->arena_off, S->d_results + r->slot);
         std::memcpy(H + desc_at[k], &d, sizeof(Desc));
         ops.push_back({D + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
         const uint32_t slot = (uint32_t)r->slot;

@@ -417,10 +417,6 @@ struct Bin64 {
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
-__device__ __forceinline__ uint64_t uni64(uint64_t x)
-{
-    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
-}
 
 // The descriptor is the same for the whole wave: read it with scalar loads so its
 // fields, and every loop bound derived from them, live in SGPRs.
