@@ -200,6 +200,26 @@ def bench_small_configs(L, synth, stream):
     return out
 
 
+def bench_mfma_variant(L, synth, stream, default_ms, golden, tuning=""):
+    """The headline solve with the int8-MFMA state-update kernel in place of the
+    default one (same tables, same value)."""
+    L.set_sweep_shape(0, 0, -1, 0, 8, -1)
+    try:
+        h = L.Prepared(synth.config_42_l1(0), 1, 0)
+        kernel = h.plan()["kernel"]
+        v = h.run(stream)
+        ms = h.kernel_ms()
+        h.close()
+    finally:
+        L.set_sweep_shape(0, 0, -1, 0, 5, -1)
+        if tuning:
+            L.load_tuning(tuning)
+        elif os.path.exists(L.TUNING_PATH) and os.environ.get("LD_TUNING", "1") != "0":
+            L.load_tuning(L.TUNING_PATH)
+    return {"kernel": kernel, "kernel_ms": ms, "vs_default_kernel": default_ms / ms,
+            "value": v, "matches_oracle": (v == golden) if golden is not None else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +228,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default="", help="load this autotuner table before measuring")
+    ap.add_argument("--kernel-variant", type=int, default=-1,
+                    help="binary sweep kernel for the headline solve: 5 or 4 (SGPR operands, that many "
+                         "low rows), 0 (VGPR operands), 8 (int8-MFMA state update); default: tuned")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
                          "known traffic, to scale the HBM counters of a profiler run)")
@@ -228,6 +251,8 @@ def main():
     stream = torch.cuda.current_stream()
     if a.tuning:
         L.load_tuning(a.tuning)
+    if a.kernel_variant >= 0:
+        L.set_sweep_shape(0, 0, -1, 0, a.kernel_variant, -1)
     M = synth.config_42_l1(0)
     h = L.Prepared(M, 1, 0)
     plan = h.plan()
@@ -276,7 +301,7 @@ def main():
         "config": {"workload": "L1 (local bound) of one 42x42 int32 matrix, entries U[-100,100], seed 0; "
                                "2^41 Gray-code steps per solve",
                    "n": 42, "m": 42, "d": 1, "marginals": 0,
-                   "plan": {k: plan[k] for k in ("mp", "R", "C", "P", "n_prefix", "i64")}},
+                   "plan": {k: plan[k] for k in ("mp", "R", "C", "P", "n_prefix", "i64", "kernel")}},
         "l1_42_seconds": ms_per_step / 1e3,
         "pct_int32_valu_peak": 100.0 * achieved / INT32_VALU_PEAK,
         "result": value,
@@ -289,6 +314,8 @@ def main():
     }
 
     if not a.no_extras:
+        print("bench: matrix-core variant", file=sys.stderr, flush=True)
+        out["mfma_variant_42"] = bench_mfma_variant(L, synth, stream, kavg, golden, a.tuning)
         print("bench: batch", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = bench_batch(L, synth)
         print("bench: serve", file=sys.stderr, flush=True)

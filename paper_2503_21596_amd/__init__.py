@@ -38,7 +38,7 @@ class ld_plan_info(ctypes.Structure):
                 ("d", ctypes.c_int32), ("transposed", ctypes.c_int32), ("i64", ctypes.c_int32),
                 ("mp", ctypes.c_int32), ("R", ctypes.c_int32), ("C", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("P_tab", ctypes.c_int32), ("n_prefix", ctypes.c_uint64),
-                ("words", ctypes.c_double)]
+                ("words", ctypes.c_double), ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ld_server_config(ctypes.Structure):

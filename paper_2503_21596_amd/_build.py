@@ -23,6 +23,9 @@ UNITS = [
     ("ld_kernels_bin.hip", ["-DLD_KIND=0"], "kbin0.o"),
     ("ld_kernels_bin.hip", ["-DLD_KIND=1"], "kbin1.o"),
     ("ld_kernels_bin.hip", ["-DLD_KIND=2"], "kbin2.o"),
+    ("ld_kernels_mfma.hip", ["-DLD_KIND=0"], "kmfma0.o"),
+    ("ld_kernels_mfma.hip", ["-DLD_KIND=1"], "kmfma1.o"),
+    ("ld_kernels_mfma.hip", ["-DLD_KIND=2"], "kmfma2.o"),
     ("ld_kernels_dary.hip", [], "kdary.o"),
     ("ld_kernels_dary_s.hip", [], "kdarys.o"),
     ("ld_plan.cpp", [], "plan.o"),

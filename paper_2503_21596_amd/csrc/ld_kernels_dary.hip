@@ -248,6 +248,9 @@ const void* lookup_bin32_kind2(int mp, int R);
 const void* lookup_bin32s_kind0(int mp, int R);
 const void* lookup_bin32s_kind1(int mp, int R);
 const void* lookup_bin32s_kind2(int mp, int R);
+const void* lookup_mfma_kind0(int mp);
+const void* lookup_mfma_kind1(int mp);
+const void* lookup_mfma_kind2(int mp);
 const void* lookup_bin64_kind0(int mp);
 const void* lookup_bin64_kind1(int mp);
 const void* lookup_bin64_kind2(int mp);
@@ -268,6 +271,16 @@ const void* kernel_bin32s(int kind, int mp, int R)
     case KIND_L1: return lookup_bin32s_kind0(mp, R);
     case KIND_MARG: return lookup_bin32s_kind1(mp, R);
     case KIND_L2: return lookup_bin32s_kind2(mp, R);
+    default: return nullptr;
+    }
+}
+
+const void* kernel_mfma(int kind, int mp)
+{
+    switch (kind) {
+    case KIND_L1: return lookup_mfma_kind0(mp);
+    case KIND_MARG: return lookup_mfma_kind1(mp);
+    case KIND_L2: return lookup_mfma_kind2(mp);
     default: return nullptr;
     }
 }

@@ -458,11 +458,19 @@ bool dary_sgpr_for(const SweepShape& sh, int d, int mp)
     return (tuned >= 0 ? tuned : sh.dary_sgpr) != 0;
 }
 
-void pick_bin32(Plan& p, const SweepShape& sh)
+int bin_variant(const Plan& p, const SweepShape& sh)
 {
     const int cls = variant_class(p.kind, p.d);
     const int tuned = cls >= 0 ? sh.variant[cls][variant_bucket(p.mp)] : -1;
-    const int sr = tuned >= 0 ? tuned : sh.sgpr_r;
+    return tuned >= 0 ? tuned : sh.sgpr_r;
+}
+
+// (the MFMA variant plans as the SGPR-operand kernel with R = 5, whose tables it
+// shares; use_mfma switches the kernel once the tables are built)
+void pick_bin32(Plan& p, const SweepShape& sh)
+{
+    int sr = bin_variant(p, sh);
+    if (sr == VARIANT_MFMA) sr = 5;
     p.kernel = sr > 0 ? kernel_bin32s(p.kind, p.mp, sr) : nullptr;
     if (p.kernel) {
         p.R = sr;
@@ -470,6 +478,28 @@ void pick_bin32(Plan& p, const SweepShape& sh)
     }
     p.R = std::max(0, bin_rmax(p.mp, p.kind) - (sh.r_drop ? 1 : 0));
     p.kernel = kernel_bin32(p.kind, p.mp, p.R);
+}
+
+// Switch an int32 binary plan built for R = 5 to the int8-MFMA kernel when its
+// operands fit: 1 <= C <= 16 mid rows, and every mid-row delta divided by the
+// step scale (2 for L1 and L_marg, whose deltas are twice an entry; 1 for L2)
+// lies in [-128, 127].  Values are the same either way.
+void use_mfma(Plan& p)
+{
+    if (p.i64 || p.wide || p.R != 5 || p.C < 1 || p.C > MFMA_MAX_C) return;
+    if (p.kind != PK_L1 && p.kind != PK_MARG && p.kind != PK_L2) return;
+    const void* k = kernel_mfma(p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : KIND_L2, p.mp);
+    if (!k) return;
+    const int sc = p.kind == PK_L2 ? 1 : 2;
+    const int RS = (p.mp + 15) & ~15;
+    for (int kk = 0; kk < p.C; ++kk)
+        for (int y = 0; y < p.mp; ++y) {
+            int32_t v;
+            std::memcpy(&v, p.blob.data() + p.off_mid + 4 * ((size_t)(2 * kk) * RS + y), 4);
+            if (v % sc != 0 || v / sc < -128 || v / sc > 127) return;
+        }
+    p.kernel = k;
+    p.mfma = 1;
 }
 
 Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
@@ -509,6 +539,7 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
     }
     p.words = (double)((uint64_t)1 << (A.n - 1));
     build_binary(p, A);
+    if (!p.wide && !p.i64 && bin_variant(p, sh) == VARIANT_MFMA) use_mfma(p);
     return p;
 }
 
@@ -744,6 +775,7 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
         }
         p.words = (double)p.n_prefix * (double)((uint64_t)1 << lowmid);
         build_binary(p, B);
+        if (!p.wide && !p.i64 && bin_variant(p, get_shape()) == VARIANT_MFMA) use_mfma(p);
         return p;
     }
 

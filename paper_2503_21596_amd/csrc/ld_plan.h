@@ -27,11 +27,13 @@ struct SweepShape {
     int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
     int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
-                               // (4 or 5); 0 selects the VGPR-operand kernel
+                               // (4 or 5); 0 selects the VGPR-operand kernel; 8 the kernel
+                               // whose state update runs on the matrix cores (int8 MFMA,
+                               // R = 5) where the problem's operands fit it
     int dary_sgpr = 1;         // 1: d-ary int32 problems use the SGPR-operand kernel where built
     // tuned kernel variant per (kind class, padded-width bucket); -1 = the setting
     // above.  Classes: 0 L1 / L_marg, 1 L2, 2 L_3, 3 L_4; buckets: mp in (16b, 16b + 16].
-    // Binary classes hold sgpr_r (0, 4, 5), d-ary classes dary_sgpr (0, 1).
+    // Binary classes hold sgpr_r (0, 4, 5, 8), d-ary classes dary_sgpr (0, 1).
     int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)
@@ -61,8 +63,13 @@ struct Plan {
     const void* kernel = nullptr;  // sweep kernel, null for PK_ZERO / PK_SUMABS
     int record = 0;                // 1: the sweep also stores every prefix's maximum
     int wide = 0;                  // 1: the wide (LDS-state, one wave per prefix) kernel
+    int mfma = 0;                  // 1: the int8-MFMA kernel (one wave sweeps two prefixes)
     size_t lds = 0;                // dynamic LDS bytes of the wide kernel
 };
+
+// prefixes one wave sweeps at a time: `lanes` for the register kernels (one per
+// lane), two for the MFMA kernel (one per lane half), one for the wide kernel
+inline uint64_t wave_prefixes(const Plan& p, uint64_t lanes) { return p.wide ? 1 : p.mfma ? 2 : lanes; }
 
 // class and bucket of SweepShape::variant for a problem (class -1: none)
 int variant_class(int kind, int d);

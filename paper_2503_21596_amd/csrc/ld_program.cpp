@@ -52,6 +52,9 @@ void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<
     if (wide) {
         per = 1;
         if (sh.item_words > 0) per = (uint64_t)std::max(1.0, std::floor(sh.item_words / 64.0 / wpp));
+    } else if (p.mfma) {
+        per = 2;
+        if (sh.item_words > 0) per = 2 * (uint64_t)std::max(1.0, std::floor(sh.item_words / wpp / 2));
     } else {
         per = sh.lanes_per_item;
         if (sh.item_words > 0) {
@@ -66,8 +69,9 @@ void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<
         it.prob = prob;
         it.count = (uint32_t)std::min<uint64_t>(per, p.n_prefix - p0);
         it.p0 = p0;
-        // a register-kernel wave covers 64 prefixes per round
-        const double rounds = wide ? it.count : std::ceil(it.count / 64.0);
+        // a register-kernel wave covers 64 prefixes per round, each lane one word
+        // of them per step; an MFMA-kernel wave covers two prefixes, 64 words per step
+        const double rounds = wide ? it.count : p.mfma ? std::ceil(it.count / 2.0) / 32.0 : std::ceil(it.count / 64.0);
         out.push_back({rounds * wpp * word_cost(p), it});
     }
 }
@@ -120,7 +124,7 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
             // items of about item_words words (one lane per prefix), but at least
             // min_items of them when the problem has that many lane-sized pieces
             const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);
-            const uint64_t lanes = p.wide ? 1 : sh.lanes_per_item;
+            const uint64_t lanes = wave_prefixes(p, sh.lanes_per_item);
             uint64_t k = 1;
             if (sh.item_words > 0) k = (uint64_t)std::max(1.0, std::floor(sh.item_words / (wpp * lanes)));
             const uint64_t kmax = std::max<uint64_t>(1, p.n_prefix / (lanes * std::max<uint32_t>(sh.min_items, 1)));

@@ -46,6 +46,10 @@ constexpr int dary_r(int mp, int d)
 // lookups; return nullptr when no instantiation exists
 const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin32s(int kind, int mp, int R);
+// int8-MFMA state-update kernel (binary kinds, int32, R = 5, C <= 16)
+const void* kernel_mfma(int kind, int mp);
+constexpr int MFMA_MAX_C = 16;
+constexpr int VARIANT_MFMA = 8;   // binary variant value selecting kernel_mfma
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
 const void* kernel_dary32s(int d, int mp);   // SGPR-operand d-ary kernel (DARY_RS low rows)

@@ -1,12 +1,18 @@
 """Checks on the gfx950 machine code of the built sweep kernels (our own build,
 disassembled with the ROCm LLVM tools; no GPU needed).
 
-The SGPR-operand kernels issue groups of scalar loads from inline assembly.  A
+1. The SGPR-operand kernels issue groups of scalar loads from inline assembly.  A
 scalar load writes its destination SGPRs some time after it issues, so a later
 load of the same group must not take its address from registers that an
 earlier, still outstanding load of the group writes: its address could change
 under it.  The compiler never emits that for its own loads; this test makes sure
-the register constraints of the hand-written groups rule it out as well."""
+the register constraints of the hand-written groups rule it out as well.
+
+2. The MFMA kernels read accumulator tiles from inline assembly (v_sad_u32).  The
+compiler inserts the wait states between an MFMA and an ordinary VALU read of its
+result, but not before an asm read, so the kernels add them by hand; the test
+counts the wait states between every MFMA and the next instruction that reads its
+destination registers."""
 import os
 import re
 import subprocess
@@ -63,6 +69,61 @@ def scan(lines):
     return bad
 
 
+MFMA = re.compile(r"\s+v_mfma\w*\s+v\[(\d+):(\d+)\]")
+VRANGE = re.compile(r"v\[(\d+):(\d+)\]")
+VONE = re.compile(r"(?<![\w\[:])v(\d+)")
+MFMA_READ_WAITS = 24   # at least the longest XDL write -> VALU read requirement
+
+
+def _vregs(text):
+    out = set()
+    for a, b in VRANGE.findall(text):
+        out |= set(range(int(a), int(b) + 1))
+    out |= {int(a) for a in VONE.findall(text)}
+    return out
+
+
+def mfma_short_reads(lines, need=MFMA_READ_WAITS):
+    """Instructions that read a VGPR written by an MFMA fewer than `need` wait
+    states after it (s_nop N counts N + 1, any other instruction 1), scanning each
+    function in program order.  Returns (function, waits, line) triples."""
+    bad = []
+    fn = None
+    pending = []   # [destination registers, wait states since the MFMA]
+    for line in lines:
+        f = FUNC.match(line)
+        if f:
+            fn, pending = f.group(1), []
+            continue
+        s = line.split("//")[0].split(";")[0].strip()
+        if not s or s.endswith(":") or s.startswith("."):
+            continue
+        op = s.split()[0]
+        operands = s[len(op):]
+        srcs = _vregs(operands.split(",", 1)[1]) if "," in operands else set()
+        for p in pending:
+            if p[0] & srcs and p[1] < need:
+                bad.append((fn, p[1], s))
+        pending = [p for p in pending if not (p[0] & srcs)]
+        w = int(s.split()[1], 0) + 1 if op == "s_nop" else 1
+        for p in pending:
+            p[1] += w
+        m = MFMA.match(" " + s)
+        if m:
+            pending.append([set(range(int(m.group(1)), int(m.group(2)) + 1)), 0])
+    return bad
+
+
+def test_mfma_scan_catches_a_short_read():
+    lines = ["0000000000000000 <k>:",
+             "\tv_mfma_i32_32x32x16_i8 v[0:15], v[16:17], v[18:19], v[0:15]",
+             "\ts_nop 7",
+             "\tv_sad_u32 v20, v3, s4, v20"]
+    assert len(mfma_short_reads(lines)) == 1
+    ok = lines[:3] + ["\ts_nop 7", "\ts_nop 7", "\tv_sad_u32 v20, v21, s4, v20", lines[3]]
+    assert mfma_short_reads(ok) == []
+
+
 def test_scan_catches_a_redirected_load():
     """The scan flags the sequence the early-clobber constraints prevent."""
     lines = ["0000000000000000 <k>:",
@@ -78,7 +139,7 @@ def test_scan_catches_a_redirected_load():
     assert scan(ok) == []
 
 
-@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o", "kdarys.o"])
+@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o", "kdarys.o", "kmfma0.o", "kmfma1.o", "kmfma2.o"])
 def test_scalar_loads_keep_their_address(obj, tmp_path):
     path = os.path.join(BUILD, obj)
     if not os.path.exists(path):
@@ -88,4 +149,17 @@ def test_scalar_loads_keep_their_address(obj, tmp_path):
     lines = _disassemble(path, tmp_path)
     assert sum(1 for l in lines if "s_load_dword" in l) > 100
     bad = scan(lines)
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("obj", ["kmfma0.o", "kmfma1.o", "kmfma2.o"])
+def test_mfma_results_wait(obj, tmp_path):
+    path = os.path.join(BUILD, obj)
+    if not os.path.exists(path):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    if not os.path.exists(f"{LLVM}/llvm-objdump"):
+        pytest.skip("ROCm LLVM tools not found")
+    lines = _disassemble(path, tmp_path)
+    assert sum(1 for l in lines if "v_mfma" in l) >= 32
+    bad = mfma_short_reads(lines)
     assert not bad, bad[:5]
