@@ -23,6 +23,7 @@ __global__ __launch_bounds__(256) void k_bin32(QArgs q)
     using B = Bin32<MP, KIND, R>;
     const uint32_t lane = threadIdx.x & 63;
     uint32_t off[B::K][B::NW][MP];
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(256) void k_bin32s(QArgs q)
 {
     using B = Bin32S<MP, KIND, R>;
     const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(256) void k_bin64(QArgs q)
 {
     using B = Bin64<MP, KIND>;
     const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {

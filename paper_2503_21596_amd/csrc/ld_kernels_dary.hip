@@ -17,6 +17,7 @@ __global__ __launch_bounds__(256) void k_dary32(QArgs q)
     using K = Dary32<MP, DD, R>;
     const uint32_t lane = threadIdx.x & 63;
     uint32_t off[K::NO][MP];
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {
@@ -42,6 +43,7 @@ template <int MP, int DD>
 __global__ __launch_bounds__(256) void k_dary64(QArgs q)
 {
     const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(256) void k_dary64(QArgs q)
 __global__ __launch_bounds__(64) void k_wide(QArgs q)
 {
     extern __shared__ int64_t lds[];
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {

@@ -15,6 +15,7 @@ __global__ __launch_bounds__(256) void k_dary32s(QArgs q)
 {
     using K = Dary32S<MP, DD, DARY_RS>;
     const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {

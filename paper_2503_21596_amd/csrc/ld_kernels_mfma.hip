@@ -208,6 +208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 {
     using B = BinMfma<MP, KIND>;
     const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
     WaveBest wb;
     Item it;
     while (next_item(q, it)) {

@@ -20,10 +20,11 @@
 //
 // There are two lanes, each with its own stream and steps: bulk and express.  A
 // request of less than about a millisecond of work goes to the express lane,
-// whose launches take at most one block per CU while bulk work runs; bulk
-// launches leave one block per CU free while there is express work (when their
-// kernel fits three or more per CU), so express work starts at once instead of
-// queueing behind bulk steps.
+// whose launches take at most one block per CU while bulk work runs, with their
+// waves at raised issue priority; bulk launches leave one block per CU free (always
+// when their kernel fits five or more per CU, else while there is express work and
+// it fits three), so express work starts at once instead of queueing behind bulk
+// steps, and runs at close to the speed of an idle SIMD.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -449,11 +450,14 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         const uint32_t resident = resident_blocks(g.first.first, threads, lds);
         const uint32_t per_cu = S->cus > 0 ? resident / (uint32_t)S->cus : 0;
         uint32_t cap = resident;
-        // express work takes one block per CU while bulk steps run, the whole
-        // device otherwise; bulk work leaves one block per CU to it while it has any
+        // express work takes one block per CU (at raised wave priority) while bulk
+        // steps run, the whole device otherwise.  Bulk work leaves one block per CU
+        // free for it: always when its kernel fits five or more per CU (a wave fewer
+        // per SIMD does not slow a VALU-bound sweep there, and an express request
+        // then never waits for a bulk step to drain), else while express work exists
         if (li == EXPRESS) {
             if (busy_steps(S->lanes[BULK]) > 0) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
-        } else if (per_cu >= 3 && express_active) {
+        } else if (per_cu >= 5 || (per_cu >= 3 && express_active)) {
             cap = resident - (uint32_t)S->cus;
         }
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, cap));

@@ -507,6 +507,14 @@ __device__ __forceinline__ void item_done(const QArgs& q, uint32_t prob, int64_t
     }
 }
 
+// Serving's express launches (q.done set) raise their waves' issue priority: they
+// share each SIMD with the waves of a long bulk launch, and at equal priority a
+// small request would be issued only its share of one wave among many.
+__device__ __forceinline__ void queue_priority(const QArgs& q)
+{
+    if (q.done != nullptr) __builtin_amdgcn_s_setprio(3);
+}
+
 // Per-wave running maximum over consecutive items of one problem.
 struct WaveBest {
     int64_t best = INT64_MIN;
