@@ -8,10 +8,22 @@
 
 namespace ld {
 
+// Waves per SIMD each instantiation is compiled for: the most whose register
+// budget (512 / waves VGPRs) still holds the d state vectors, the subset scores and
+// the temporaries of the Gray loop without spilling inside it (checked in the built
+// code, see the ISA tests).  Left to itself the compiler spends the registers on
+// scheduling freedom instead, and runs d = 3 at 36-40 columns and d = 4 at 28 with
+// two waves, which leaves a quarter of the VALU issue slots idle.
+constexpr int dary_s_waves(int mp, int d)
+{
+    if (d == 3) return mp <= 28 ? 4 : mp <= 40 ? 3 : 2;
+    return mp <= 16 ? 4 : mp <= 28 ? 3 : 2;
+}
+
 // Persistent queue kernel (see k_bin32): one item = a range of prefixes of one
 // problem, one lane per prefix.
 template <int MP, int DD>
-__global__ __launch_bounds__(256) void k_dary32s(QArgs q)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_waves(MP, DD)))) void k_dary32s(QArgs q)
 {
     using K = Dary32S<MP, DD, DARY_RS>;
     const uint32_t lane = threadIdx.x & 63;

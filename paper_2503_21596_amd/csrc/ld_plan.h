@@ -24,7 +24,7 @@ struct SweepShape {
     int dary_cwords = 4096;  // target d^C words per lane for d >= 3
     int c_target = 0;        // > 0: binary prefixes of 2^c_target words (mid + low rows), the
                              // rest of the rows become prefix rows (batch planning)
-    int dary_lanes = 1 << 17;  // d >= 3: move mid rows into the prefix until this many
+    int dary_lanes = 1 << 19;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
     int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel; 8 the kernel

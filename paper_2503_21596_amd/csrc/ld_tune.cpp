@@ -84,12 +84,12 @@ double time_batch(const Cal& c)
     return best;
 }
 
-double time_plain(const std::vector<int32_t>& M, int n, int m)
+double time_plain(const std::vector<int32_t>& M, int n, int m, int d = 1)
 {
     double best = 1e30;
     for (int rep = 0; rep < 3; ++rep) {
         const double t0 = now_s();
-        if (ld_norm(M.data(), n, m, 1, 0) == INT64_MIN) return 1e30;
+        if (ld_norm(M.data(), n, m, d, 0) == INT64_MIN) return 1e30;
         best = std::min(best, now_s() - t0);
     }
     return best;
@@ -108,9 +108,10 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
     std::fprintf(f,
                  "  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
-                 "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"plain_p_min\": %d,\n  \"measured\": [%s]\n}\n",
+                 "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"plain_p_min\": %d,\n"
+                 "  \"plain_dary_lanes\": %d,\n  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
-                 t.plain_r_drop, t.sgpr_r, t.plain_p_min, notes.c_str());
+                 t.plain_r_drop, t.sgpr_r, t.plain_p_min, t.plain_dary_lanes, notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -145,6 +146,7 @@ void set_tuning(const Tuning& t)
     s.c_goal = t.plain_c_goal;
     s.r_drop = t.plain_r_drop;
     s.sgpr_r = t.sgpr_r;
+    s.dary_lanes = t.plain_dary_lanes;
     std::memcpy(s.variant, t.variant, sizeof s.variant);
     set_shape(s);
 }
@@ -251,6 +253,32 @@ int ld_autotune(const char* path, double budget_seconds)
     }
     set_tuning(best);
 
+    // plain calls, d >= 3: lane count, timed on an L_3 problem of 22 x 32 and an
+    // L_4 problem of 18 x 24 (sum of the two times)
+    {
+        Rng r{0xd3a};
+        std::vector<int32_t> A((size_t)22 * 32), B((size_t)18 * 24);
+        for (auto& v : A) v = r.uniform(-100, 100);
+        for (auto& v : B) v = r.uniform(-100, 100);
+        double bt = 1e30;
+        Tuning bp = best;
+        for (int lanes : {1 << 17, 1 << 18, 1 << 19}) {
+            if (now_s() > t_end) break;
+            Tuning t = best;
+            t.plain_dary_lanes = lanes;
+            set_tuning(t);
+            const double dt = time_plain(A, 22, 32, 3) + time_plain(B, 18, 24, 4);
+            std::snprintf(buf, sizeof buf, ", {\"dary_lanes\": %d, \"ms\": %.3f}", lanes, 1e3 * dt);
+            notes += buf;
+            if (dt < bt) {
+                bt = dt;
+                bp = t;
+            }
+        }
+        best = bp;
+    }
+    set_tuning(best);
+
     // kernel variant per kind class and width bucket (binary: SGPR-operand kernel
     // with 5 or 4 low rows, VGPR-operand kernel, int8-MFMA kernel; d-ary: SGPR- or
     // VGPR-operand kernel), timed on one problem each of
@@ -326,6 +354,7 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "plain_c_goal", &v)) t.plain_c_goal = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
     if (read_key(text, "sgpr_r", &v)) t.sgpr_r = (v == 4 || v == 5 || v == VARIANT_MFMA) ? (int)v : 0;
+    if (read_key(text, "plain_dary_lanes", &v)) t.plain_dary_lanes = (int)std::max(0.0, std::min(v, 1073741824.0));
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < 4; ++b) {
             char key[32];

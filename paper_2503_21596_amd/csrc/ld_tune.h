@@ -15,6 +15,8 @@ struct Tuning {
     int plain_c_goal = 12;        // plain calls: aim for 2^this words per prefix
     int plain_r_drop = 0;         // plain calls: one low row fewer than the register budget allows
     int sgpr_r = 5;               // int32 binary kinds: low rows of the SGPR-operand kernel (0: VGPR kernel)
+    int plain_dary_lanes = 1 << 19;  // plain calls, d >= 3: trade mid rows for prefix rows until
+                                     // this many lanes exist
     // kernel variant per (kind class, width bucket), as SweepShape::variant (-1: the above)
     int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
 };

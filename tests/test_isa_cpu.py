@@ -12,7 +12,11 @@ the register constraints of the hand-written groups rule it out as well.
 compiler inserts the wait states between an MFMA and an ordinary VALU read of its
 result, but not before an asm read, so the kernels add them by hand; the test
 counts the wait states between every MFMA and the next instruction that reads its
-destination registers."""
+destination registers.
+
+3. The d-ary SGPR-operand kernels are compiled for a number of waves per SIMD
+chosen per width; the Gray loop (the innermost loop that scores subsets) must
+not spill at that register budget."""
 import os
 import re
 import subprocess
@@ -163,3 +167,57 @@ def test_mfma_results_wait(obj, tmp_path):
     assert sum(1 for l in lines if "v_mfma" in l) >= 32
     bad = mfma_short_reads(lines)
     assert not bad, bad[:5]
+
+
+DEPTH = re.compile(r"^\s*;.*Depth=(\d+)")
+DARY_S = re.compile(r"^(_ZN2ld9k_dary32sILi(\d+)ELi(\d+)EEEvNS_5QArgsE):")
+
+
+def gray_loop_spills(asm_lines):
+    """Per k_dary32s instantiation of a compiler assembly listing: scratch
+    instructions at the deepest loop level that holds v_sad_u32 (the Gray loop)."""
+    out = {}
+    cur = None
+    depth = 0
+    for line in asm_lines:
+        m = DARY_S.match(line)
+        if m:
+            cur = (int(m.group(2)), int(m.group(3)))
+            out[cur] = {"sad": {}, "scratch": {}}
+            depth = 0
+            continue
+        if cur is None:
+            continue
+        if line.startswith(".Lfunc_end"):
+            cur = None
+            continue
+        if re.match(r"^\.LBB\d+_\d+:", line):
+            depth = 0
+            continue
+        d = DEPTH.match(line)
+        if d:
+            depth = int(d.group(1))
+            continue
+        if "v_sad_u32" in line:
+            out[cur]["sad"][depth] = out[cur]["sad"].get(depth, 0) + 1
+        if "scratch_" in line:
+            out[cur]["scratch"][depth] = out[cur]["scratch"].get(depth, 0) + 1
+    return {k: v["scratch"].get(max(v["sad"]), 0) for k, v in out.items() if v["sad"]}
+
+
+def test_dary_gray_loop_has_no_spills(tmp_path):
+    """Compiles the d-ary SGPR-operand kernels as the build does (same flags, full
+    device pipeline) and keeps the compiler's assembly listing, whose loop-depth
+    annotations locate the Gray loop."""
+    build = pytest.importorskip("paper_2503_21596_amd._build")
+    if not os.path.exists(build.HIPCC):
+        pytest.skip("hipcc not found")
+    src = os.path.join(build.CSRC, "ld_kernels_dary_s.hip")
+    cmd = [build.HIPCC] + build.COMMON + build.DEVICE + ["-x", "hip", "-c", src, "-o", str(tmp_path / "kds.o"),
+                                                        "--save-temps"]
+    subprocess.run(cmd, check=True, capture_output=True, cwd=tmp_path)
+    listing = [f for f in os.listdir(tmp_path) if f.endswith(".s") and "gfx950" in f]
+    assert len(listing) == 1, os.listdir(tmp_path)
+    spills = gray_loop_spills(open(tmp_path / listing[0]).read().splitlines())
+    assert len(spills) == 23, sorted(spills)   # d = 3: 4 .. 52 columns, d = 4: 4 .. 40
+    assert all(v == 0 for v in spills.values()), {k: v for k, v in spills.items() if v}
