@@ -576,11 +576,27 @@ ld_server* ld_server_create(const ld_server_config* cfg_in)
     int count = 0;
     bool ok = hipGetDeviceCount(&count) == hipSuccess && cfg.device >= 0 && cfg.device < count &&
               hipSetDevice(cfg.device) == hipSuccess && device_ok(nullptr);
-    for (auto& ln : S->lanes) ok = ok && hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess;
     {
         hipDeviceProp_t prop;
         ok = ok && hipGetDeviceProperties(&prop, cfg.device) == hipSuccess;
         if (ok) S->cus = prop.multiProcessorCount;
+    }
+    // The lanes' streams must run on different hardware queues, or express
+    // launches would wait behind bulk ones in one in-order queue.  A process has
+    // few hardware queues (4 by default) and streams beyond that share them, so
+    // plain streams created after others (a batch's graph, prepared handles) can
+    // land on the same queue.  A stream with a CU mask gets a queue of its own;
+    // the mask here enables every CU.
+    if (ok) {
+        std::vector<uint32_t> mask((size_t)(S->cus + 31) / 32, 0xffffffffu);
+        if (S->cus % 32) mask.back() = (1u << (S->cus % 32)) - 1;
+        for (auto& ln : S->lanes) {
+            if (hipExtStreamCreateWithCUMask(&ln.stream, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+                ln.stream = nullptr;
+                ok = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) == hipSuccess;
+            }
+            if (!ok) break;
+        }
     }
     ok = ok && hipMalloc((void**)&S->arena_dev, cfg.arena_bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&S->d_descs, sizeof(Desc) * cfg.max_inflight_problems) == hipSuccess;
