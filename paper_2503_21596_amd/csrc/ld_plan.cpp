@@ -674,20 +674,24 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
             ++C;
         }
     // a single problem should fill the device: trade mid rows for prefix rows
-    // (more lanes, fewer words each) while few lanes exist, keeping at least two
-    // mid rows and about 2^12 words per lane (a lane's start costs about as much
-    // as scoring a few hundred words)
+    // (more lanes, fewer words each).  Up to 2^17 lanes (two waves per SIMD) the
+    // trade goes on down to two mid rows; beyond that, up to dary_lanes, only while
+    // each lane keeps about 2^12 words, since a lane's start costs about as much as
+    // scoring a few hundred words
     if (sh.dary_lanes > 0) {
         auto lanes = [&](int pt, int pf) { return rgs_count(pt, d) * std::pow((double)d, pf); };
-        int c_floor = 2;
-        while (std::pow((double)d, c_floor + p.R) < 4096.0) ++c_floor;
-        while (C > c_floor && lanes(p.P_tab, P) < (double)sh.dary_lanes) {
+        auto trade = [&]() {
             if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)(1 << 20))
                 ++p.P_tab;
             else
                 ++P;
             --C;
-        }
+        };
+        const double fill = std::min((double)sh.dary_lanes, (double)(1 << 17));
+        while (C > 2 && lanes(p.P_tab, P) < fill) trade();
+        int c_floor = 2;
+        while (std::pow((double)d, c_floor + p.R) < 4096.0) ++c_floor;
+        while (C > c_floor && lanes(p.P_tab, P) < (double)sh.dary_lanes) trade();
     }
     p.C = C;
     p.P = P;
