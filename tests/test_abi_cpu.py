@@ -219,3 +219,32 @@ def test_tuning_file_round_trip(tmp_path):
         L.load_tuning(L.TUNING_PATH)
     p = L.plan(M, 1, 0)
     assert p["R"] == 5 and p["P"] == 20
+
+
+def test_plan_dary_lane_trading():
+    """Plain d-ary calls trade mid rows for lanes (prefixes) in two stages: down to
+    two mid rows until 2^17 lanes exist, then up to 2^19 lanes only while a lane
+    keeps at least 2^12 words (d^(C+R) >= 4096).  Values never depend on this."""
+    def lane_words(p, d):
+        return d ** (p["C"] + p["R"])
+
+    # small: fills 2^17 lanes as far as two mid rows allow
+    p = L.plan(synth.config_pm(0), 3, 0)
+    assert p["C"] == 2 or p["n_prefix"] >= 2 ** 17, p
+    # mid-size d = 3: more lanes than 2^17, each still long
+    M = synth.matrix(95, 22, 40, -100, 100, "ab")
+    p = L.plan(M, 3, 0)
+    assert p["n_prefix"] > 2 ** 17 and lane_words(p, 3) >= 4096, p
+    # large d = 3: already beyond 2^19 lanes with long lanes, so nothing moves
+    M = synth.matrix(155, 24, 40, -100, 100, "ab")
+    p = L.plan(M, 3, 0)
+    assert p["n_prefix"] >= 2 ** 19 and lane_words(p, 3) >= 4096, p
+    # d = 4 near the floor: the second stage stops at 4^(C + 3) = 4096
+    M = synth.matrix(102, 17, 30, -100, 100, "ab")
+    p = L.plan(M, 4, 0)
+    assert lane_words(p, 4) >= 4096 or p["n_prefix"] < 2 ** 17, p
+    for d, n, m in [(3, 22, 40), (3, 20, 40), (4, 18, 16), (4, 19, 30)]:
+        p = L.plan(synth.matrix(55 + n + m, n, m, -100, 100, "ab"), d, 0)
+        assert p["C"] >= 2
+        if p["n_prefix"] > 2 ** 17:
+            assert lane_words(p, d) >= 4096, (d, n, m, p)
