@@ -248,3 +248,25 @@ def test_plan_dary_lane_trading():
         assert p["C"] >= 2
         if p["n_prefix"] > 2 ** 17:
             assert lane_words(p, d) >= 4096, (d, n, m, p)
+
+
+def test_plan_kernel_family_and_mfma_selection():
+    """ld_plan_info.kernel names the sweep kernel: the headline takes the SGPR-operand
+    kernel (1); with variant 8 the int8-MFMA kernel (2) where the mid-row deltas fit
+    int8 and 1 <= C <= 16, else the SGPR-operand kernel with 5 low rows."""
+    M = synth.config_42_l1(0)
+    p = L.plan(M, 1, 0)
+    assert p["kernel"] == 1 and p["R"] == 5
+    try:
+        L.set_sweep_shape(0, 0, -1, 0, 8, -1)
+        p = L.plan(M, 1, 0)
+        assert p["kernel"] == 2 and p["R"] == 5 and p["C"] == 16
+        big = synth.matrix(4, 20, 20, -1000, 1000, "abi")      # deltas 2 * 1000 do not fit int8
+        p = L.plan(big, 1, 0)
+        assert p["kernel"] == 1 and p["R"] == 5
+        assert L.plan(synth.matrix(5, 20, 20, -120, 120, "abi"), 2, 0)["kernel"] == 2
+        assert L.plan(synth.matrix(6, 12, 20, -9, 9, "abi"), 3, 0)["kernel"] in (0, 1)   # d >= 3: d-ary
+        assert L.plan(synth.matrix(7, 3, 70, 1, 9, "abi"), 1, 0)["kernel"] == 4          # > 64 columns: wide
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+    assert L.plan(M, 1, 0)["kernel"] == 1
