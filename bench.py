@@ -231,6 +231,9 @@ def main():
     ap.add_argument("--kernel-variant", type=int, default=-1,
                     help="binary sweep kernel for the headline solve: 5 or 4 (SGPR operands, that many "
                          "low rows), 0 (VGPR operands), 8 (int8-MFMA state update); default: tuned")
+    ap.add_argument("--solve", default="",
+                    help="D,N,M: instead of the benchmark, time one solve of L_D on a seeded N x M matrix "
+                         "(entries U[-100,100]) and print its plan and kernel time (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
                          "known traffic, to scale the HBM counters of a profiler run)")
@@ -249,6 +252,17 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.solve:
+        d, n, m = (int(x) for x in a.solve.split(","))
+        Ms = synth.matrix(91 + n + m, n, m, -100, 100, "prof")
+        hs = L.Prepared(Ms, d, 0)
+        value = [hs.run(stream) for _ in range(2)][-1]
+        plan = hs.plan()
+        print(json.dumps({"solve": {"d": d, "n": n, "m": m, "value": value, "kernel_ms": hs.kernel_ms(),
+                                    "plan": {k: plan[k] for k in ("kernel", "mp", "R", "C", "P", "P_tab",
+                                                                  "n_prefix", "words")}}}), flush=True)
+        hs.close()
+        return
     if a.tuning:
         L.load_tuning(a.tuning)
     if a.kernel_variant >= 0:
