@@ -22,8 +22,9 @@
 // prefix (i / 4) % 2, and its A row is that column of the mid-row deltas.
 //
 // Accumulators hold true value + 2^31 (wrapping int32 arithmetic, exact while
-// sum |M| < 2^31, as in the VALU kernels); |true value| is one v_sad_u32 against
-// 2^31.  The tables are the R = 5 tables of the VGPR-state kernels.
+// sum |M| < 2^31, as in the VALU kernels; the matrix cores wrap int32 sums the
+// same way); |true value| is one v_sad_u32 against 2^31.  The tables are those of
+// the SGPR-operand kernel with R = 5 (row stride RS), read here per lane.
 #include <hip/hip_runtime.h>
 #include <utility>
 
