@@ -210,6 +210,12 @@ void ld_server_destroy(ld_server* s);
 int ld_plan(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
             ld_plan_info* info);
 
+/* Plan a problem as ld_norm_batch and ld_batch_prepare plan each member (the
+ * batch sweep shape: tuned words per prefix and prefix cap per problem).
+ * Returns LD_OK or an error code. */
+int ld_plan_batch(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals,
+                  ld_plan_info* info);
+
 /* Gray-code digits as the kernels compute them (Sec. 2.1.2, 2.3.2).
  * ld_gray_digit: digit i of word j of the d-ary reflected Gray code (d = 2: the
  * binary reflected code, Eq. (Hamming_equation)).

@@ -43,6 +43,7 @@ def _load():
                            ("oracle_ld_all", [P, i32, i32, i32, i32]),
                            ("oracle_range", [P, i32, i32, i32, i32, i32, u64, u64, i32]),
                            ("oracle_l1_split", [P, i32, i32, i32, i32]),
+                           ("oracle_ld_split", [P, i32, i32, i32, i32]),
                            ("oracle_value_of", [P, i32, i32, i32, i32, P])]:
             f = getattr(lib, name)
             f.argtypes = args
@@ -106,6 +107,18 @@ def l1_split(M, marginals: int = 0, threads: int = 0) -> int:
     a = _mat(M)
     return int(_load().oracle_l1_split(a.ctypes.data, a.shape[0], a.shape[1], marginals,
                                        _threads(threads)))
+
+
+def ld_split(M, d: int, threads: int = 0) -> int:
+    a = _mat(M)
+    return int(_load().oracle_ld_split(a.ctypes.data, a.shape[0], a.shape[1], d, _threads(threads)))
+
+
+def norm_split(M, d: int, marginals: int = 0, threads: int = 0) -> int:
+    """The same value as norm(), by the split-table forms (for the larger inputs)."""
+    if d == 1:
+        return l1_split(M, marginals, threads)
+    return ld_split(M, d, threads)
 
 
 def value_of(M, d: int, marginals: int, assignment) -> int:

@@ -24,8 +24,10 @@
  *
  * Parity status of every function is pinned by tests/test_oracle_pins.py
  * (printed values of the worked example, closed forms, brute force over both
- * parties, invariances); oracle_l1_split is pinned by agreement with oracle_l1
- * on every input small enough for both.
+ * parties, invariances); oracle_l1_split and oracle_ld_split are pinned by
+ * agreement with oracle_l1 / oracle_lmarg / oracle_ld on inputs small enough for
+ * both and large enough that several tiles of both tables, and ragged thread
+ * ranges, are visited.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -299,6 +301,104 @@ int64_t oracle_l1_split(const int32_t* M, int n, int m, int marg, int nthreads)
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, split_worker, &jobs[t]);
     split_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    int64_t best = INT64_MIN;
+    for (int t = 0; t < nthreads; ++t)
+        if (jobs[t].best > best) best = jobs[t].best;
+    free(TA); free(TB);
+    return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* Split-table direct enumeration for L_d, d >= 2 (Eqs. (L_o_norm), (ma)).
+ *
+ * Still evaluates the definition for every assignment with row 0 fixed to
+ * message 0: the free rows 1..n-1 are split into a lower half A and an upper
+ * half B.  For every assignment p of A's rows (a base-d counter) the table
+ * TA[p][k][y] holds the column sums of the rows sent to message k, row 0
+ * included; TB[q][k][y] holds the same for B's rows.  The per-message column
+ * sums of the full assignment (p, q) are TA[p][k][y] + TB[q][k][y], and its
+ * value is the sum over k and y of their absolute values.  int64 throughout. */
+
+typedef struct {
+    const int64_t* TA; const int64_t* TB;
+    uint64_t na, nb_lo, nb_hi;
+    int w;             /* d * m entries per table row */
+    int64_t best;
+} ldsplit_job_t;
+
+static void* ldsplit_worker(void* arg)
+{
+    ldsplit_job_t* j = (ldsplit_job_t*)arg;
+    const int w = j->w;
+    int64_t best = INT64_MIN;
+    for (uint64_t q0 = j->nb_lo; q0 < j->nb_hi; q0 += TILE_Q) {
+        const uint64_t q1 = q0 + TILE_Q < j->nb_hi ? q0 + TILE_Q : j->nb_hi;
+        for (uint64_t p0 = 0; p0 < j->na; p0 += TILE_P) {
+            const uint64_t p1 = p0 + TILE_P < j->na ? p0 + TILE_P : j->na;
+            for (uint64_t q = q0; q < q1; ++q) {
+                const int64_t* tb = j->TB + q * (uint64_t)w;
+                for (uint64_t p = p0; p < p1; ++p) {
+                    const int64_t* ta = j->TA + p * (uint64_t)w;
+                    int64_t total = 0;
+                    for (int e = 0; e < w; ++e) total += iabs64(ta[e] + tb[e]);
+                    if (total > best) best = total;
+                }
+            }
+        }
+    }
+    j->best = best;
+    return NULL;
+}
+
+/* Tabulate, for every assignment of rows r0..r0+k-1 to messages (digit i of the
+ * base-d counter p is the message of row r0+i), the per-message column sums
+ * T[p][msg][y]; with with_row0 set, row 0 is added to message 0. */
+static void tabulate_dary(int64_t* T, const int32_t* M, int m, int d, int r0, int k, int with_row0)
+{
+    const uint64_t cnt = ipow((uint64_t)d, k);
+    const int w = d * m;
+    for (uint64_t p = 0; p < cnt; ++p) {
+        int64_t* t = T + p * (uint64_t)w;
+        for (int e = 0; e < w; ++e) t[e] = 0;
+        if (with_row0)
+            for (int y = 0; y < m; ++y) t[y] += M[y];
+        uint64_t c = p;
+        for (int i = 0; i < k; ++i) {
+            const int msg = (int)(c % (uint64_t)d);
+            c /= (uint64_t)d;
+            const int32_t* row = M + (size_t)(r0 + i) * m;
+            for (int y = 0; y < m; ++y) t[(size_t)msg * m + y] += row[y];
+        }
+    }
+}
+
+int64_t oracle_ld_split(const int32_t* M, int n, int m, int d, int nthreads)
+{
+    if (n <= 0 || m <= 0) return 0;
+    if (d < 2) return INT64_MIN;
+    const int f = n - 1;      /* free rows 1..n-1 */
+    const int ka = f / 2, kb = f - ka;
+    const uint64_t na = ipow((uint64_t)d, ka), nb = ipow((uint64_t)d, kb);
+    const int w = d * m;
+    int64_t* TA = (int64_t*)malloc(na * (uint64_t)w * sizeof(int64_t));
+    int64_t* TB = (int64_t*)malloc(nb * (uint64_t)w * sizeof(int64_t));
+    if (!TA || !TB) { free(TA); free(TB); return INT64_MIN; }
+    tabulate_dary(TA, M, m, d, 1, ka, 1);
+    tabulate_dary(TB, M, m, d, 1 + ka, kb, 0);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((uint64_t)nthreads > nb) nthreads = (int)nb;
+    ldsplit_job_t jobs[256];
+    pthread_t th[256];
+    uint64_t per = nb / (uint64_t)nthreads, rem = nb % (uint64_t)nthreads, at = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        uint64_t len = per + ((uint64_t)t < rem ? 1 : 0);
+        jobs[t] = (ldsplit_job_t){TA, TB, na, at, at + len, w, INT64_MIN};
+        at += len;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, ldsplit_worker, &jobs[t]);
+    ldsplit_worker(&jobs[0]);
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
     int64_t best = INT64_MIN;
     for (int t = 0; t < nthreads; ++t)

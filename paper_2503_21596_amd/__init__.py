@@ -69,6 +69,7 @@ SIGNATURES = {
     "ld_last_error": (ctypes.c_int, []),
     "ld_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ld_plan": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
+    "ld_plan_batch": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P]),
     "ld_gray_digit": (_U32, [_U32, _U32, _U64]),
     "ld_gray_change": (_I32, [_U32, _U64, _P, _P]),
     "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32, _I32, _I32]),
@@ -283,10 +284,12 @@ class Batch:
             pass
 
 
-def plan(M, d: int = 1, marginals: int = 0) -> dict:
+def plan(M, d: int = 1, marginals: int = 0, batch: bool = False) -> dict:
+    """The plan ld_norm makes for M (batch=True: the plan of a batch member)."""
     a = _mat(M)
     info = ld_plan_info()
-    rc = lib().ld_plan(a.ctypes.data, a.shape[0], a.shape[1], int(d), int(marginals), ctypes.byref(info))
+    f = lib().ld_plan_batch if batch else lib().ld_plan
+    rc = f(a.ctypes.data, a.shape[0], a.shape[1], int(d), int(marginals), ctypes.byref(info))
     out = {f[0]: getattr(info, f[0]) for f in ld_plan_info._fields_}
     out["status"] = rc
     out["kind_name"] = PLAN_KINDS.get(info.kind, "?")

@@ -142,7 +142,7 @@ struct ld_prepared {
     float last_ms = 0.f;
 };
 
-namespace {
+namespace ld {
 
 void info_from_plan(const Plan& p, ld_plan_info* info)
 {
@@ -167,6 +167,10 @@ void info_from_plan(const Plan& p, ld_plan_info* info)
     else if (p.kind == PK_LD) info->kernel = p.kernel == kernel_dary32s(p.d, p.mp) ? 1 : 0;
     else info->kernel = p.kernel == kernel_bin32s(p.kind, p.mp, p.R) ? 1 : 0;
 }
+
+}  // namespace ld
+
+namespace {
 
 void release(ld_prepared* h)
 {
@@ -276,6 +280,7 @@ const char* ld_error_string(int code)
     case LD_EBUSY: return "server busy";
     case LD_PENDING: return "result pending";
     case LD_ENOTFOUND: return "unknown ticket";
+    case LD_ECANCELED: return "request cancelled";
     default: return "unknown error code";
     }
 }

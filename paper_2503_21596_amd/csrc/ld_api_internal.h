@@ -5,6 +5,7 @@
 
 #include <vector>
 
+#include "ld.h"
 #include "ld_plan.h"
 #include "ld_program.h"
 
@@ -20,5 +21,8 @@ bool device_ok(int* dev);
 bool run_plans_sync(const std::vector<const Plan*>& plans, const ItemShape& shape, int64_t* out, hipStream_t s);
 
 int64_t run_plan_sync(const Plan& p);
+
+// the public description of a plan
+void info_from_plan(const Plan& p, ld_plan_info* info);
 
 }  // namespace ld

@@ -77,6 +77,14 @@ void release(ld_batch* b)
 
 extern "C" {
 
+int ld_plan_batch(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals, ld_plan_info* info)
+{
+    if (!info) return LD_EINVAL;
+    Plan p = make_plan(M, n, m, d, marginals, batch_shape_for(n, m, d));
+    info_from_plan(p, info);
+    return p.status;
+}
+
 int ld_norm_batch(const ld_problem* probs, int32_t count, int64_t* out, int32_t* status, void* hip_stream)
 {
     if (count < 0 || (count > 0 && (!probs || !out))) {

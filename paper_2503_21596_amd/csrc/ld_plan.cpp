@@ -693,6 +693,13 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
         while (std::pow((double)d, c_floor + p.R) < 4096.0) ++c_floor;
         while (C > c_floor && lanes(p.P_tab, P) < (double)sh.dary_lanes) trade();
     }
+    // the register kernels count a lane's d^C Gray words in 32 bits: move mid rows
+    // back into the prefix until d^C < 2^32 (the batch prefix cap above can push C
+    // past that; values do not depend on the split)
+    while (C > 0 && std::pow((double)d, C) > 4294967295.0) {
+        --C;
+        ++P;
+    }
     p.C = C;
     p.P = P;
     std::vector<uint64_t> tab;

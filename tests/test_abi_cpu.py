@@ -270,3 +270,30 @@ def test_plan_kernel_family_and_mfma_selection():
     finally:
         L.load_tuning(L.TUNING_PATH)
     assert L.plan(M, 1, 0)["kernel"] == 1
+
+
+def test_batch_plan_dary_step_count_fits_32_bits(tmp_path):
+    """The d-ary register kernels count a lane's d^C Gray words in 32 bits.  A batch
+    prefix cap moves prefix rows into the Gray walk; the planner must still keep
+    d^C < 2^32 (moving rows back into the prefix), whatever the tuned cap."""
+    path = tmp_path / "cap.json"
+    path.write_text('{"batch_pfx_cap": 16, "dary_cwords": 729, "measured": []}')
+    try:
+        L.load_tuning(str(path))
+        for d, n, m in [(3, 36, 12), (4, 30, 12), (5, 28, 12), (3, 24, 20), (6, 20, 8)]:
+            M = synth.matrix(d * 100 + n, n, m, -100, 100, "cap")
+            p = L.plan(M, d, 0, batch=True)
+            assert p["status"] == L.LD_OK, (d, n, p)
+            assert d ** p["C"] < 2 ** 32, (d, n, p)
+            # the prefix rows and the walk still cover every restricted-growth class
+            assert p["words"] == L.plan(M, d, 0)["words"], (d, n)
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+
+
+def test_error_strings_cover_every_code(lib):
+    texts = {code: lib.ld_error_string(code).decode() for code in range(9)}
+    fallback = lib.ld_error_string(99).decode()
+    assert fallback == "unknown error code"
+    assert fallback not in texts.values(), texts
+    assert len(set(texts.values())) == 9

@@ -349,12 +349,120 @@ def test_edges():
 # the split-table form and the prefix-range form against the plain enumeration
 
 
+# The split-table forms visit the pairs (p, q) of half-assignments in tiles of
+# 512 p-values by 64 q-values, and split the q-values into one contiguous range per
+# thread.  The sizes below reach several tiles of both tables (n = 22..26: 2^10 ..
+# 2^12 p-values), a single partial p-tile (n <= 19) and ragged thread ranges
+# (3 and 7 threads).
+SPLIT_TILE_P, SPLIT_TILE_Q = 512, 64
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_split_table_agrees(seed):
     n = 3 + 3 * seed
     M = rnd(seed, n, 7, -30, 30)
     assert oracle.l1_split(M, 0) == oracle.l1(M)
     assert oracle.l1_split(M, 1) == oracle.lmarg(M)
+
+
+@pytest.mark.parametrize("n,m,threads", [(22, 9, 8), (24, 7, 3), (24, 6, 7), (26, 5, 8)])
+def test_split_table_agrees_multi_tile(n, m, threads):
+    M = rnd(n * 10 + m, n, m, -30, 30)
+    assert (1 << ((n - 1) // 2)) > SPLIT_TILE_P
+    assert oracle.l1_split(M, 0, threads) == oracle.l1(M)
+    assert oracle.l1_split(M, 1, threads) == oracle.lmarg(M)
+
+
+@pytest.mark.parametrize("d,n,m,threads", [(2, 22, 6, 8), (2, 23, 5, 3), (3, 14, 5, 7), (3, 15, 4, 8),
+                                           (4, 11, 4, 3), (5, 8, 3, 8), (2, 3, 4, 8), (4, 3, 3, 2),
+                                           (2, 1, 3, 1), (3, 2, 2, 4), (6, 7, 3, 5)])
+def test_ld_split_agrees(d, n, m, threads):
+    M = rnd(d * 100 + n, n, m, -30, 30)
+    assert oracle.ld_split(M, d, threads) == oracle.ld(M, d)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ld_split_bob_outputs_bruteforce(seed):
+    n, m, d = 3 + seed % 2, 2 + seed % 3, 2 + seed % 3
+    M = rnd(seed + 40, n, m)
+    assert oracle.ld_split(M, d) == bf_ld_with_b(M, d)
+
+
+def _split_position(n, radix, p, q):
+    """Assignment digits whose half-assignments are p (rows 1..ka) and q (rows
+    ka+1..n-1), digit i of p / q (base radix) belonging to the i-th row of its half;
+    row 0 takes digit 1 (a_0 = +1) for radix 2 and message 0 otherwise."""
+    f = n - 1
+    ka = f // 2
+    digits = [1 if radix == 2 else 0]
+    for i in range(ka):
+        digits.append(p // radix ** i % radix)
+    for i in range(f - ka):
+        digits.append(q // radix ** i % radix)
+    return np.array(digits)
+
+
+def _ragged_q(nb, threads):
+    """A q-value inside the last (partial) q-tile of thread 0's range."""
+    per, rem = divmod(nb, threads)
+    length = per + (1 if rem else 0)
+    return length - 1 if length % SPLIT_TILE_Q else length - SPLIT_TILE_Q // 2
+
+
+@pytest.mark.parametrize("where", ["last_p_ragged_q", "first_p_last_q", "mid"])
+@pytest.mark.parametrize("marg", [0, 1])
+def test_split_planted_maximum(where, marg):
+    """A matrix K a* v^T + E with small noise E has its maximum at a = a* only (up to
+    the global sign, removed by a_0 = +1): for a != a*, |a . a*| <= n - 2, which
+    costs 2K sum|v| > 2 n sum_y max|E_.y|.  Placing a* in a chosen tile of the split
+    form makes a skipped or misplaced tile visible."""
+    n, m, threads = 24, 6, 7
+    ka, kb = (n - 1) // 2, (n - 1) - (n - 1) // 2
+    na, nb = 1 << ka, 1 << kb
+    if where == "last_p_ragged_q":
+        p, q = na - 1, _ragged_q(nb, threads)
+    elif where == "first_p_last_q":
+        p, q = 0, nb - 1
+    else:
+        p, q = 1234 % na, 2345 % nb
+    a = np.where(_split_position(n, 2, p, q) == 1, 1, -1).astype(np.int64)
+    v = synth.uniform_ints(synth.stream_key(p + q, "planted_v"), m, 1, 3) * \
+        np.where(synth.uniform_ints(synth.stream_key(p, "planted_s"), m, 0, 1) == 0, -1, 1)
+    v[0] = abs(v[0])
+    E = rnd(q + 7, n, m, -2, 2).astype(np.int64)
+    K = 100
+    assert 2 * K * np.abs(v).sum() > 2 * n * m * 2
+    M = (K * np.outer(a, v) + E).astype(np.int32)
+    s = a @ M.astype(np.int64)
+    want = int(s[0] + np.abs(s[1:]).sum()) if marg else int(np.abs(s).sum())
+    assert oracle.l1_split(M, marg, threads) == want
+    assert (oracle.lmarg(M) if marg else oracle.l1(M)) == want
+
+
+@pytest.mark.parametrize("d,n,threads", [(2, 22, 7), (3, 14, 3), (4, 11, 5)])
+@pytest.mark.parametrize("where", ["last_p_ragged_q", "first_p_last_q"])
+def test_ld_split_planted_maximum(d, n, threads, where):
+    """Rows K h_{t(x)} + E_x built from d rows h_k of an 8 x 8 Hadamard matrix.  Two
+    Hadamard rows differ in half of the columns, so a message holding c >= 1 rows
+    of type k and one row of another type has norm 8Kc, the same as without that
+    row: every row away from its own type's group costs 8K.  The maximum is
+    therefore at the planted grouping t (up to relabelling the messages), as long
+    as the noise moves each value by less than 4K."""
+    m = 8
+    H = np.array([[1]], dtype=np.int64)
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    ka, kb = (n - 1) // 2, (n - 1) - (n - 1) // 2
+    na, nb = d ** ka, d ** kb
+    p, q = (na - 1, _ragged_q(nb, threads)) if where == "last_p_ragged_q" else (0, nb - 1)
+    t = _split_position(n, d, p, q)
+    K = 200
+    E = rnd(p + 3 * q, n, m, -2, 2).astype(np.int64)
+    assert 2 * n * m * 2 < 4 * K
+    M = (K * H[t] + E).astype(np.int32)
+    want = int(sum(np.abs(M[t == k].astype(np.int64).sum(axis=0)).sum() for k in range(d)))
+    assert oracle.ld_split(M, d, threads) == want
+    assert oracle.ld(M, d) == want
 
 
 @pytest.mark.parametrize("d,marg", [(1, 0), (1, 1), (2, 0), (3, 0)])
