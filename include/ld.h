@@ -131,7 +131,8 @@ typedef struct {
     uint64_t n_prefix;    /* prefixes, i.e. lane-sized work units */
     double words;         /* assignments scored */
     int32_t kernel;       /* sweep kernel: 0 VGPR operands, 1 SGPR operands, 2 int8-MFMA
-                             state update, 3 int64, 4 wide (LDS state), -1 none */
+                             state update, 3 int64, 4 wide (LDS state), 5 packed 16-bit
+                             (two columns per register), -1 none */
     int32_t reserved;
 } ld_plan_info;
 
@@ -230,10 +231,13 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
  * register budget of the VGPR-operand kernel allows; dary_ptab: rows covered by
  * restricted-growth prefixes (<= 16); sgpr_r: low rows scored per state by the
  * int32 binary kernel that reads its low-row operands from SGPRs (4 or 5), 0
- * for the kernel that holds them in VGPRs, or 8 for the kernel whose Gray-code
+ * for the kernel that holds them in VGPRs, 8 for the kernel whose Gray-code
  * state update runs on the matrix cores (int8 MFMA, 5 low rows; used where every
  * mid-row delta fits int8 and there are 1 to 16 mid rows, else the SGPR kernel
- * with 5 low rows runs); dary_sgpr: 1 for the d-ary kernel with
+ * with 5 low rows runs), or 16 for the kernel that holds two columns per register
+ * as 16-bit halves (5 low rows; used where every column has sum_x |M_xy| <= 32767,
+ * and for L_marg column 0 at most 21844, else the SGPR kernel with 5 low rows
+ * runs); dary_sgpr: 1 for the d-ary kernel with
  * SGPR operands (d = 3, 4, three low rows) where it is built, 0 for the VGPR one.
  * An explicit sgpr_r or dary_sgpr also replaces the autotuner's per-width choices
  * for those kinds.  Values never depend on the shape. */

@@ -44,10 +44,13 @@ def _load():
                            ("oracle_range", [P, i32, i32, i32, i32, i32, u64, u64, i32]),
                            ("oracle_l1_split", [P, i32, i32, i32, i32]),
                            ("oracle_ld_split", [P, i32, i32, i32, i32]),
+                           ("oracle_ld_classes", [P, i32, i32, i32, i32]),
                            ("oracle_value_of", [P, i32, i32, i32, i32, P])]:
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = i64
+        lib.oracle_rgs_count.argtypes = [i32, i32]
+        lib.oracle_rgs_count.restype = u64
         _lib = lib
     return _lib
 
@@ -112,6 +115,16 @@ def l1_split(M, marginals: int = 0, threads: int = 0) -> int:
 def ld_split(M, d: int, threads: int = 0) -> int:
     a = _mat(M)
     return int(_load().oracle_ld_split(a.ctypes.data, a.shape[0], a.shape[1], d, _threads(threads)))
+
+
+def ld_classes(M, d: int, threads: int = 0) -> int:
+    """L_d by one assignment per relabelling class (restricted-growth strings)."""
+    a = _mat(M)
+    return int(_load().oracle_ld_classes(a.ctypes.data, a.shape[0], a.shape[1], d, _threads(threads)))
+
+
+def rgs_count(n: int, d: int) -> int:
+    return int(_load().oracle_rgs_count(n, d))
 
 
 def norm_split(M, d: int, marginals: int = 0, threads: int = 0) -> int:

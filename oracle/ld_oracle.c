@@ -15,7 +15,9 @@
  * Symmetry reductions used (Sec. 2.1.2 for L1, Sec. 2.3.2 for L_d):
  *   L1 is unchanged under a -> -a, so row 0 is fixed to +1;
  *   L_marg fixes row 0 to +1 by its own definition;
- *   L_d is unchanged under relabelling of the messages, so row 0 is fixed to 0.
+ *   L_d is unchanged under relabelling of the messages, so row 0 is fixed to 0
+ *   (oracle_ld), or only one assignment per relabelling class is scored
+ *   (oracle_ld_classes, for alphabets too large for d^(n-1) assignments).
  * The *_all variants fix nothing and enumerate all 2^n / d^n assignments; tests
  * use them to pin the symmetry reductions.
  *
@@ -27,7 +29,8 @@
  * parties, invariances); oracle_l1_split and oracle_ld_split are pinned by
  * agreement with oracle_l1 / oracle_lmarg / oracle_ld on inputs small enough for
  * both and large enough that several tiles of both tables, and ragged thread
- * ranges, are visited.
+ * ranges, are visited; oracle_ld_classes by agreement with oracle_ld and
+ * oracle_ld_all, and its class count by the Stirling numbers of the second kind.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -307,6 +310,97 @@ int64_t oracle_l1_split(const int32_t* M, int n, int m, int marg, int nthreads)
         if (jobs[t].best > best) best = jobs[t].best;
     free(TA); free(TB);
     return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* L_d over one assignment per relabelling class.
+ *
+ * Eq. (L_o_norm) is unchanged when the d messages are permuted, so every
+ * assignment has the value of the one whose messages appear in first-use order:
+ * a_0 = 0 and each a_x at most one above max(a_0 .. a_{x-1}) (a restricted-growth
+ * string).  These strings are walked in lexicographic order; string number c is
+ * scored by thread c mod nthreads, each with the plain per-assignment score. */
+
+/* next restricted-growth string after a[0..n-1] with digits below d; 0 when a is
+ * the last one */
+static int rgs_next(int8_t* a, int n, int d)
+{
+    for (int i = n - 1; i >= 1; --i) {
+        int mx = 0;
+        for (int k = 0; k < i; ++k)
+            if (a[k] > mx) mx = a[k];
+        const int top = mx + 1 < d - 1 ? mx + 1 : d - 1;
+        if (a[i] < top) {
+            ++a[i];
+            for (int k = i + 1; k < n; ++k) a[k] = 0;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+typedef struct {
+    const int32_t* M;
+    int n, m, d, t, nthreads;
+    int64_t best;
+    uint64_t count;
+} cls_job_t;
+
+static void* cls_worker(void* arg)
+{
+    cls_job_t* j = (cls_job_t*)arg;
+    int8_t a[256];
+    memset(a, 0, sizeof a);
+    int64_t best = INT64_MIN;
+    uint64_t c = 0, mine = 0;
+    do {
+        if (c % (uint64_t)j->nthreads == (uint64_t)j->t) {
+            const int64_t v = j->M ? score_dary(j->M, j->n, j->m, j->d, a) : 0;
+            if (v > best) best = v;
+            ++mine;
+        }
+        ++c;
+    } while (rgs_next(a, j->n, j->d));
+    j->best = best;
+    j->count = mine;
+    return NULL;
+}
+
+static int64_t run_classes(const int32_t* M, int n, int m, int d, int nthreads, uint64_t* count)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    cls_job_t jobs[256];
+    pthread_t th[256];
+    for (int t = 0; t < nthreads; ++t) jobs[t] = (cls_job_t){M, n, m, d, t, nthreads, INT64_MIN, 0};
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, cls_worker, &jobs[t]);
+    cls_worker(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    int64_t best = INT64_MIN;
+    uint64_t total = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].best > best) best = jobs[t].best;
+        total += jobs[t].count;
+    }
+    if (count) *count = total;
+    return best;
+}
+
+int64_t oracle_ld_classes(const int32_t* M, int n, int m, int d, int nthreads)
+{
+    if (n <= 0 || m <= 0) return 0;
+    if (d < 2 || n > 256) return INT64_MIN;
+    return run_classes(M, n, m, d, nthreads, NULL);
+}
+
+/* number of restricted-growth strings of length n with digits below d, counted by
+ * the same walk (the number of relabelling classes) */
+uint64_t oracle_rgs_count(int n, int d)
+{
+    if (n <= 0 || d < 1 || n > 256) return 0;
+    uint64_t cnt = 0;
+    run_classes(NULL, n, 1, d, 1, &cnt);
+    return cnt;
 }
 
 /* ------------------------------------------------------------------ */

@@ -163,6 +163,7 @@ void info_from_plan(const Plan& p, ld_plan_info* info)
     if (!p.kernel) info->kernel = -1;
     else if (p.wide) info->kernel = 4;
     else if (p.mfma) info->kernel = 2;
+    else if (p.pack16) info->kernel = 5;
     else if (p.i64) info->kernel = 3;
     else if (p.kind == PK_LD) info->kernel = p.kernel == kernel_dary32s(p.d, p.mp) ? 1 : 0;
     else info->kernel = p.kernel == kernel_bin32s(p.kind, p.mp, p.R) ? 1 : 0;
@@ -327,7 +328,7 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
     if (dary_ptab > 0) s.dary_ptab = std::min(dary_ptab, 16);
     // an explicit variant replaces the tuned per-width choices of its kinds
     if (sgpr_r >= 0) {
-        s.sgpr_r = sgpr_r == VARIANT_MFMA ? VARIANT_MFMA : std::min(sgpr_r, MAX_RS);
+        s.sgpr_r = (sgpr_r == VARIANT_MFMA || sgpr_r == VARIANT_PACK16) ? sgpr_r : std::min(sgpr_r, MAX_RS);
         for (int c = 0; c < 2; ++c)
             for (int b = 0; b < 4; ++b) s.variant[c][b] = -1;
     }

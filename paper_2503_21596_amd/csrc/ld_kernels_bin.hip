@@ -73,6 +73,35 @@ __global__ __launch_bounds__(256) void k_bin32s(QArgs q)
     wb.flush();
 }
 
+// Same queue loop over the packed 16-bit sweep (Bin16S); scores carry the
+// descriptor's bias, removed before they are published.
+template <int MW, int KIND, int R>
+__global__ __launch_bounds__(256) void k_bin16s(QArgs q)
+{
+    using B = Bin16S<MW, KIND, R>;
+    const uint32_t lane = threadIdx.x & 63;
+    queue_priority(q);
+    WaveBest wb;
+    Item it;
+    while (next_item(q, it)) {
+        const Desc D = load_desc(q.descs + it.prob);
+        wb.enter(it.prob, D.result);
+        uint32_t best = B::best_init();
+        const uint32_t rounds = (it.count + 63) >> 6;
+        for (uint32_t j = 0; j < rounds; ++j) {
+            uint32_t i = lane + 64 * j;
+            if (i >= it.count) i = it.count - 1;
+            uint32_t pb = B::best_init();
+            B::prefix(D, D.pfx_base + it.p0 + i, pb);
+            best = B::better(best, pb);
+            if (D.rec) D.rec[it.p0 + i] = B::finish(pb, D.bias);
+        }
+        wb.add(B::finish(best, D.bias));
+        wb.item_end(q);
+    }
+    wb.flush();
+}
+
 template <int MP, int KIND>
 __global__ __launch_bounds__(256) void k_bin64(QArgs q)
 {
@@ -106,6 +135,7 @@ constexpr int NMP = MAX_MP / 2;   // mp = 2, 4, ..., 64
 const void* g_bin32[NMP][MAX_R + 1] = {};
 const void* g_bin32s[NMP][MAX_RS + 1] = {};
 const void* g_bin64[MAX_MP / 8] = {};
+const void* g_bin16s[MAX_MP / 2] = {};   // words 1 .. 32 (L1 and L2 only)
 
 template <int MP, int R>
 void reg_one()
@@ -123,6 +153,8 @@ void reg_mp()
     if constexpr (MP % 8 == 0) g_bin64[MP / 8 - 1] = (const void*)&k_bin64<MP, LD_KIND>;
     g_bin32s[MP / 2 - 1][4] = (const void*)&k_bin32s<MP, LD_KIND, 4>;
     g_bin32s[MP / 2 - 1][5] = (const void*)&k_bin32s<MP, LD_KIND, 5>;
+    // packed kernels by word count MP / 2 (L_marg plans use the L1 ones)
+    if constexpr (LD_KIND != KIND_MARG) g_bin16s[MP / 2 - 1] = (const void*)&k_bin16s<MP / 2, LD_KIND, PACK16_R>;
 }
 
 template <int... I>
@@ -150,6 +182,12 @@ const void* LD_CAT(lookup_bin32s_kind, LD_KIND)(int mp, int R)
 {
     if (mp < 2 || mp > MAX_MP || (mp & 1) || R < 0 || R > MAX_RS) return nullptr;
     return g_bin32s[mp / 2 - 1][R];
+}
+
+const void* LD_CAT(lookup_bin16s_kind, LD_KIND)(int words)
+{
+    if (words < 1 || words > MAX_MP / 2) return nullptr;
+    return g_bin16s[words - 1];
 }
 
 const void* LD_CAT(lookup_bin64_kind, LD_KIND)(int mp)

@@ -251,6 +251,8 @@ const void* lookup_bin32_kind2(int mp, int R);
 const void* lookup_bin32s_kind0(int mp, int R);
 const void* lookup_bin32s_kind1(int mp, int R);
 const void* lookup_bin32s_kind2(int mp, int R);
+const void* lookup_bin16s_kind0(int words);
+const void* lookup_bin16s_kind2(int words);
 const void* lookup_mfma_kind0(int mp);
 const void* lookup_mfma_kind1(int mp);
 const void* lookup_mfma_kind2(int mp);
@@ -274,6 +276,16 @@ const void* kernel_bin32s(int kind, int mp, int R)
     case KIND_L1: return lookup_bin32s_kind0(mp, R);
     case KIND_MARG: return lookup_bin32s_kind1(mp, R);
     case KIND_L2: return lookup_bin32s_kind2(mp, R);
+    default: return nullptr;
+    }
+}
+
+const void* kernel_bin16s(int kind, int words)
+{
+    switch (kind) {
+    case KIND_L1:
+    case KIND_MARG: return lookup_bin16s_kind0(words);
+    case KIND_L2: return lookup_bin16s_kind2(words);
     default: return nullptr;
     }
 }

@@ -253,7 +253,48 @@ void build_binary(Plan& p, const Mat& A)
     }
     auto delta = [&](int x, int y) -> int64_t { return y < m ? v1(x, y) - v0(x, y) : 0; };
 
-    if (!p.i64) {
+    if (!p.i64 && p.pack16) {
+        // two columns per dword: halves offset by 2^15; a delta dword is
+        // d_lo + 2^16 d_hi modulo 2^32; L_marg's column 0 carries the offset h
+        // (state + h, operand - h) so that its term is x + 2h = x + bias
+        const int MW = mp / 2;
+        const int RS = (MW + 15) & ~15;
+        const int K = l2 ? 2 : 1;
+        const int64_t h = p.bias / 2, H = 1 << 15;
+        auto half = [](int64_t v) { return (uint32_t)((uint64_t)v & 0xffffu); };
+        auto pack = [&](int64_t lo, int64_t hi) { return half(lo) | (half(hi) << 16); };
+        auto dpack = [](int64_t lo, int64_t hi) { return (uint32_t)(uint64_t)(lo + hi * 65536); };
+        p.off_base = 0;
+        p.off_hid = align256(p.off_base + 4 * (size_t)MW);
+        p.off_mid = align256(p.off_hid + 4 * (size_t)std::max(P, 1) * RS);
+        p.off_offs = align256(p.off_mid + 4 * (size_t)std::max(C, 1) * 2 * RS);
+        p.off_tab = align256(p.off_offs + 4 * (size_t)K * NW * RS);
+        p.blob.assign(p.off_tab, 0);
+        for (int j = 0; j < MW; ++j)
+            put<uint32_t>(p.blob, p.off_base, j, pack(base[2 * j] + H + (j == 0 ? h : 0), base[2 * j + 1] + H));
+        for (int hh = 0; hh < P; ++hh)
+            for (int j = 0; j < MW; ++j)
+                put<uint32_t>(p.blob, p.off_hid, (size_t)hh * RS + j,
+                              dpack(delta(high0 + hh, 2 * j), delta(high0 + hh, 2 * j + 1)));
+        for (int k = 0; k < C; ++k)
+            for (int j = 0; j < MW; ++j) {
+                const int64_t a = delta(mid0 + k, 2 * j), b = delta(mid0 + k, 2 * j + 1);
+                put<uint32_t>(p.blob, p.off_mid, (size_t)(2 * k) * RS + j, dpack(a, b));
+                put<uint32_t>(p.blob, p.off_mid, (size_t)(2 * k + 1) * RS + j, dpack(-a, -b));
+            }
+        for (int w = 0; w < NW; ++w) {
+            std::vector<int64_t> low(mp, 0);
+            for (int y = 0; y < m; ++y)
+                for (int i = 0; i < R; ++i) low[y] += ((w >> i) & 1) ? v1(1 + i, y) : v0(1 + i, y);
+            for (int j = 0; j < MW; ++j) {
+                put<uint32_t>(p.blob, p.off_offs, (size_t)w * RS + j,
+                              pack(H - low[2 * j] - (j == 0 ? h : 0), H - low[2 * j + 1]));
+                if (l2)
+                    put<uint32_t>(p.blob, p.off_offs, (size_t)(NW + w) * RS + j,
+                                  pack(H + total[2 * j] - low[2 * j], H + total[2 * j + 1] - low[2 * j + 1]));
+            }
+        }
+    } else if (!p.i64) {
         const int RS = (mp + 15) & ~15;
         const int K = l2 ? 2 : 1;
         p.off_base = 0;
@@ -465,11 +506,39 @@ int bin_variant(const Plan& p, const SweepShape& sh)
     return tuned >= 0 ? tuned : sh.sgpr_r;
 }
 
+// The packed 16-bit kernel needs every column sum and operand to fit 16 bits offset
+// by 2^15: sum_x |M_xy| <= 2^15 - 1 for every column, and for L_marg's linear
+// column 0 also its offset h = ceil(B_0 / 2) on top (B_0 + h <= 2^15 - 1).  On
+// success p.bias = 2h (L_marg) or 0.
+bool pack16_fits(Plan& p, const Mat& A)
+{
+    for (int y = 0; y < A.m; ++y) {
+        int64_t b = 0;
+        for (int x = 0; x < A.n; ++x) b += std::abs((int64_t)A.at(x, y));
+        const int64_t h = (p.kind == PK_MARG && y == 0) ? (b + 1) / 2 : 0;
+        if (b + h > PACK16_BOUND) return false;
+        if (p.kind == PK_MARG && y == 0) p.bias = (int32_t)(2 * h);
+    }
+    return true;
+}
+
 // (the MFMA variant plans as the SGPR-operand kernel with R = 5, whose tables it
 // shares; use_mfma switches the kernel once the tables are built)
-void pick_bin32(Plan& p, const SweepShape& sh)
+void pick_bin32(Plan& p, const SweepShape& sh, Mat const& A)
 {
     int sr = bin_variant(p, sh);
+    if (sr == VARIANT_PACK16) {
+        p.bias = 0;
+        const void* k = pack16_fits(p, A) ? kernel_bin16s(p.kind == PK_L2 ? KIND_L2 : KIND_L1, p.mp / 2) : nullptr;
+        if (k) {
+            p.kernel = k;
+            p.pack16 = 1;
+            p.R = PACK16_R;
+            return;
+        }
+        p.bias = 0;
+        sr = 5;
+    }
     if (sr == VARIANT_MFMA) sr = 5;
     p.kernel = sr > 0 ? kernel_bin32s(p.kind, p.mp, sr) : nullptr;
     if (p.kernel) {
@@ -516,7 +585,7 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
             p.R = 0;
             p.kernel = kernel_bin64(p.kind, p.mp);
         } else {
-            pick_bin32(p, sh);
+            pick_bin32(p, sh, A);
         }
     }
     if (!p.kernel) {
@@ -761,7 +830,7 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
             if (p.i64)
                 p.kernel = kernel_bin64(p.kind, p.mp);
             else
-                pick_bin32(p, get_shape());
+                pick_bin32(p, get_shape(), A);
         }
         if (!p.kernel) {
             p.R = 0;
@@ -848,6 +917,7 @@ Desc make_desc(const Plan& p, const void* dev_blob, int64_t* result)
     D.C = p.C;
     D.P = p.P;
     D.P_tab = p.P_tab;
+    D.bias = p.bias;
     D.pfx_base = p.pfx_base;
     D.n_prefix = p.n_prefix;
     D.dpow_free = p.dpow_free;

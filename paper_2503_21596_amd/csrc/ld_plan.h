@@ -29,11 +29,12 @@ struct SweepShape {
     int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel; 8 the kernel
                                // whose state update runs on the matrix cores (int8 MFMA,
-                               // R = 5) where the problem's operands fit it
+                               // R = 5) where the problem's operands fit it; 16 the packed
+                               // 16-bit kernel (R = 5) where every column bound fits it
     int dary_sgpr = 1;         // 1: d-ary int32 problems use the SGPR-operand kernel where built
     // tuned kernel variant per (kind class, padded-width bucket); -1 = the setting
     // above.  Classes: 0 L1 / L_marg, 1 L2, 2 L_3, 3 L_4; buckets: mp in (16b, 16b + 16].
-    // Binary classes hold sgpr_r (0, 4, 5, 8), d-ary classes dary_sgpr (0, 1).
+    // Binary classes hold sgpr_r (0, 4, 5, 8, 16), d-ary classes dary_sgpr (0, 1).
     int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)
@@ -64,6 +65,8 @@ struct Plan {
     int record = 0;                // 1: the sweep also stores every prefix's maximum
     int wide = 0;                  // 1: the wide (LDS-state, one wave per prefix) kernel
     int mfma = 0;                  // 1: the int8-MFMA kernel (one wave sweeps two prefixes)
+    int pack16 = 0;                // 1: the packed 16-bit kernel (two columns per dword)
+    int32_t bias = 0;              // packed L_marg: constant in every score (Desc::bias)
     size_t lds = 0;                // dynamic LDS bytes of the wide kernel
 };
 

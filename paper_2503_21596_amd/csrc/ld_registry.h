@@ -46,6 +46,12 @@ constexpr int dary_r(int mp, int d)
 // lookups; return nullptr when no instantiation exists
 const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin32s(int kind, int mp, int R);
+// packed 16-bit kernel (two columns per dword; L1 and, through it, L_marg, and L2),
+// by dword count; PACK16_R low rows
+constexpr int PACK16_R = 5;
+constexpr int VARIANT_PACK16 = 16;   // binary variant value selecting kernel_bin16s
+constexpr int64_t PACK16_BOUND = 32767;   // largest sum_x |M_xy| of a column it takes
+const void* kernel_bin16s(int kind, int words);
 // int8-MFMA state-update kernel (binary kinds, int32, R = 5, C <= 16)
 const void* kernel_mfma(int kind, int mp);
 constexpr int MFMA_MAX_C = 16;

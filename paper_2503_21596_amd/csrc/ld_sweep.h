@@ -60,6 +60,16 @@ __device__ __forceinline__ uint32_t sad_u32_s(uint32_t a, uint32_t b, uint32_t a
     return r;
 }
 
+// v_sad_u16 with the operand b taken from an SGPR.  On gfx950 it adds the absolute
+// differences of both 16-bit halves, taken as unsigned values, to a 32-bit
+// accumulator: |a[15:0] - b[15:0]| + |a[31:16] - b[31:16]| + acc.
+__device__ __forceinline__ uint32_t sad_u16_s(uint32_t a, uint32_t b, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_sad_u16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(acc));
+    return r;
+}
+
 // Compile-time loop: f(integral_constant<int, i>) for i = 0 .. N-1, so that
 // offsets derived from i can be immediates of a load.
 template <class F, int... I>
@@ -351,6 +361,121 @@ struct Bin32S {
         if constexpr (KIND == KIND_MARG) return (int64_t)(int32_t)best;
         else return (int64_t)best;
     }
+};
+
+// ---------------------------------------------------------------------------
+// binary kinds, int32 path, two columns per register (packed 16-bit), low-row
+// operands streamed through SGPRs
+//
+// When every column has sum_x |M_xy| <= 2^15 - 1, every column sum and every
+// low-row operand fits 16 bits offset by 2^15, so one dword holds two columns
+// (column 2j in the low half).  One v_sad_u16 then scores two columns of a word,
+// which halves the scoring instructions of Bin32S.  A row update stays one 32-bit
+// add per dword: the stored delta is d_2j + 2^16 d_2j+1 modulo 2^32, and since both
+// new halves lie in [0, 2^16) no carry crosses between them.
+// L_marg runs through the L1 instantiation: its linear column 0 is stored with an
+// offset h >= half its bound, so the term |x + 2h| equals x + 2h for every
+// reachable x; the descriptor's bias (2h) is subtracted from the maximum.
+template <int MW, int KIND, int R>
+struct Bin16S {
+    static constexpr int NW = 1 << R;
+    static constexpr int K = (KIND == KIND_L2) ? 2 : 1;
+    static constexpr int RS = (MW + 15) & ~15;   // row stride of every table, dwords
+    static constexpr int N8 = (MW + 7) / 8;      // 8-dword chunks of a row
+    static_assert(R >= 2, "four operand streams per group");
+    static_assert(KIND == KIND_L1 || KIND == KIND_L2, "L_marg runs as L1 with a bias");
+
+    __device__ static constexpr uint32_t best_init() { return 0u; }
+    __device__ static __forceinline__ uint32_t better(uint32_t a, uint32_t b) { return max(a, b); }
+
+    template <int S0, int S1, int S2, int S3, int C8>
+    __device__ static __forceinline__ void chunk4(const uint32_t (&s)[MW], uint64_t ob, uint32_t (&a)[4])
+    {
+        u32x8 o0, o1, o2, o3;
+        sload_4x8<(S0 * RS + 8 * C8) * 4, (S1 * RS + 8 * C8) * 4, (S2 * RS + 8 * C8) * 4,
+                  (S3 * RS + 8 * C8) * 4>(ob, o0, o1, o2, o3);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            constexpr int y0 = 8 * C8;
+            if (y0 + j >= MW) continue;
+            const uint32_t x = s[y0 + j];
+            a[0] = sad_u16_s(x, o0[j], a[0]);
+            a[1] = sad_u16_s(x, o1[j], a[1]);
+            a[2] = sad_u16_s(x, o2[j], a[2]);
+            a[3] = sad_u16_s(x, o3[j], a[3]);
+        }
+    }
+
+    __device__ static __forceinline__ void score(const uint32_t (&s)[MW], uint64_t ob, uint32_t& best)
+    {
+        if constexpr (KIND == KIND_L2) {
+            static_for<NW / 2>([&](auto h) {
+                constexpr int w = 2 * h;
+                uint32_t a[4] = {0, 0, 0, 0};
+                static_for<N8>([&](auto c) { chunk4<w, NW + w, w + 1, NW + w + 1, c>(s, ob, a); });
+                best = max(best, max(a[0] + a[1], a[2] + a[3]));
+            });
+        } else {
+            static_for<NW / 4>([&](auto g) {
+                constexpr int w = 4 * g;
+                uint32_t a[4] = {0, 0, 0, 0};
+                static_for<N8>([&](auto c) { chunk4<w, w + 1, w + 2, w + 3, c>(s, ob, a); });
+                best = max(max(best, max(a[0], a[1])), max(a[2], a[3]));
+            });
+        }
+    }
+
+    // s += the row at `row` (RS dwords, wave-uniform address)
+    __device__ static __forceinline__ void add_row(uint32_t (&s)[MW], uint64_t row)
+    {
+        static_for<(N8 + 3) / 4>([&](auto q) {
+            constexpr int c0 = 4 * q;
+            constexpr int n = (N8 - c0) < 4 ? (N8 - c0) : 4;
+            u32x8 r[4];
+            if constexpr (n == 4)
+                sload_4x8<32 * c0, 32 * (c0 + 1), 32 * (c0 + 2), 32 * (c0 + 3)>(row, r[0], r[1], r[2], r[3]);
+            else if constexpr (n == 3) {
+                sload_2x8<32 * c0, 32 * (c0 + 1)>(row, r[0], r[1]);
+                sload_1x8<32 * (c0 + 2)>(row, r[2]);
+            } else if constexpr (n == 2)
+                sload_2x8<32 * c0, 32 * (c0 + 1)>(row, r[0], r[1]);
+            else
+                sload_1x8<32 * c0>(row, r[0]);
+#pragma unroll
+            for (int i = 0; i < n; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (8 * (c0 + i) + j < MW) s[8 * (c0 + i) + j] += r[i][j];
+        });
+    }
+
+    // Sweep one prefix value v: start state, then the Gray walk over 2^C words of
+    // the mid rows, scoring the 2^R low patterns at each word.
+    __device__ static __forceinline__ void prefix(const Desc& D, uint64_t v, uint32_t& best)
+    {
+        cptr<uint32_t> base = as_const<uint32_t>(D.base);
+        cptr<uint32_t> hid = as_const<uint32_t>(D.hid);
+        uint32_t s[MW];
+#pragma unroll
+        for (int y = 0; y < MW; ++y) s[y] = base[y];
+        for (int h = 0; h < D.P; ++h) {
+            const uint32_t mask = 0u - (uint32_t)((v >> h) & 1u);
+#pragma unroll
+            for (int y = 0; y < MW; ++y) s[y] += mask & hid[h * RS + y];
+        }
+        const uint64_t ob = (uint64_t)(uintptr_t)D.offs;
+        const uint64_t mb = (uint64_t)(uintptr_t)D.mid;
+        const uint32_t nsteps = 1u << D.C;
+        for (uint32_t t = 0;;) {
+            score(s, ob, best);
+            if (++t == nsteps) break;
+            const uint32_t k = brgc_changed(t);
+            const uint32_t g = brgc_digit(k, t);   // new value of digit k
+            add_row(s, mb + __builtin_amdgcn_readfirstlane((uint32_t)((2 * k + (1 - g)) * (RS * 4))));
+        }
+    }
+
+    __device__ static __forceinline__ int64_t finish(uint32_t best, int32_t bias) { return (int64_t)best - bias; }
 };
 
 // ---------------------------------------------------------------------------

@@ -228,7 +228,7 @@ int ld_autotune(const char* path, double budget_seconds)
         for (auto& v : B) v = r.uniform(-100, 100);
         double bt = 1e30;
         Tuning bp = best;
-        for (int sr : {5, 4, 0})
+        for (int sr : {VARIANT_PACK16, 5, 4, 0})
             for (int pm : {16, 18, 19})
                 for (int p : {20, 22})
                     for (int c : {12, 14}) {
@@ -279,8 +279,9 @@ int ld_autotune(const char* path, double budget_seconds)
     }
     set_tuning(best);
 
-    // kernel variant per kind class and width bucket (binary: SGPR-operand kernel
-    // with 5 or 4 low rows, VGPR-operand kernel, int8-MFMA kernel; d-ary: SGPR- or
+    // kernel variant per kind class and width bucket (binary: packed 16-bit kernel,
+    // SGPR-operand kernel with 5 or 4 low rows, VGPR-operand kernel, int8-MFMA
+    // kernel; d-ary: SGPR- or
     // VGPR-operand kernel), timed on one problem each of
     // a few milliseconds (L1 with 33 rows, L2 with 32, L_3 with 19, L_4 with 15;
     // width 16b + 14, or square for the narrowest L1 bucket so that the planner
@@ -296,7 +297,7 @@ int ld_autotune(const char* path, double budget_seconds)
                 std::vector<int32_t> M((size_t)n * m);
                 for (auto& x : M) x = r.uniform(-100, 100);
                 std::vector<int> options =
-                    c < 2 ? std::vector<int>{5, 4, 0, VARIANT_MFMA} : std::vector<int>{1, 0};
+                    c < 2 ? std::vector<int>{VARIANT_PACK16, 5, 4, 0, VARIANT_MFMA} : std::vector<int>{1, 0};
                 double bt = 1e30;
                 int pick = -1;
                 for (int o : options) {
@@ -353,7 +354,8 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "plain_p_min", &v)) t.plain_p_min = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_c_goal", &v)) t.plain_c_goal = std::max(0, std::min(40, (int)v));
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
-    if (read_key(text, "sgpr_r", &v)) t.sgpr_r = (v == 4 || v == 5 || v == VARIANT_MFMA) ? (int)v : 0;
+    if (read_key(text, "sgpr_r", &v))
+        t.sgpr_r = (v == 4 || v == 5 || v == VARIANT_MFMA || v == VARIANT_PACK16) ? (int)v : 0;
     if (read_key(text, "plain_dary_lanes", &v)) t.plain_dary_lanes = (int)std::max(0.0, std::min(v, 1073741824.0));
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < 4; ++b) {

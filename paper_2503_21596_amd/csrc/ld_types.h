@@ -26,6 +26,10 @@ constexpr int MAX_D = 8;        // widest message alphabet with a register-resid
 //    offs[K][2^R][MP]    per low-row pattern w: the value o with |s - o| equal to
 //                        the column term of the word (s, w); K = 2 for L2
 //                        (the two terms |g| and |c - g|), else 1
+//    packed 16-bit int32 path: the same tables with two columns per dword (column
+//    2j in bits 0..15, 2j+1 in bits 16..31), states and operands offset by 2^15,
+//    and each stored delta the integer d_2j + 2^16 d_2j+1 modulo 2^32, so that one
+//    32-bit add moves both columns; it needs sum_x |M_xy| <= 2^15 - 1 per column
 //  d-ary (d >= 3): state g_k = column sums of the rows sent as message k
 //    base[MP]            group-0 start: every mid row is at Gray digit 0
 //    hid[P_tab+P][MP]    the prefix rows (restricted-growth table rows, then
@@ -45,6 +49,8 @@ struct Desc {
     int32_t R, C, P;    // low / mid / high row counts
     int32_t P_tab;      // d-ary restricted-growth prefix rows
     int32_t inst;       // kernel instantiation index
+    int32_t bias;       // packed 16-bit kernels: constant added to every score (the
+                        // linear column of L_marg is scored as |x + bias|, x >= -bias)
     uint64_t pfx_base;
     uint64_t n_prefix;
     uint64_t dpow_free; // d^P (d-ary)

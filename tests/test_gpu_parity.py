@@ -198,12 +198,13 @@ def test_dary_kernel_variants(dary_sgpr):
         L.set_sweep_shape(0, 0, -1, 0, -1, 1)
 
 
-@pytest.mark.parametrize("sgpr_r", [0, 4, 5])
+@pytest.mark.parametrize("sgpr_r", [0, 4, 5, 16])
 def test_binary_kernel_variants(sgpr_r):
-    """Both int32 binary kernels (low-row operands in VGPRs, or streamed through
-    SGPRs with 4 or 5 low rows) against the oracle for L1, L_marg and L2, over
-    every column-chunk shape (m = 1 .. 64 in steps that hit each remainder mod 8)
-    and row counts below, at and above the low-row count."""
+    """The int32 binary kernels (low-row operands in VGPRs, or streamed through
+    SGPRs with 4 or 5 low rows, or two columns per register as 16-bit halves)
+    against the oracle for L1, L_marg and L2, over every column-chunk shape
+    (m = 1 .. 64 in steps that hit each remainder mod 8) and row counts below, at
+    and above the low-row count."""
     say("binary variants", sgpr_r)
     try:
         L.set_sweep_shape(0, 0, -1, 0, sgpr_r, -1)
@@ -214,10 +215,59 @@ def test_binary_kernel_variants(sgpr_r):
             for d, marg in [(1, 0), (1, 1), (2, 0)]:
                 p = L.plan(M, d, marg)
                 if p["i64"] == 0 and sgpr_r and p["kind"] != 4 and p["mp"] <= 64 and p["n"] > 1:
-                    assert p["R"] == sgpr_r, p
+                    assert p["R"] == (5 if sgpr_r == 16 else sgpr_r), p
+                if sgpr_r == 16 and p["kind_name"] in ("L1", "L2") and p["n"] > 1:
+                    assert p["kernel"] == 5, p           # every column sum fits 16 bits here
                 check(M, d, marg)
     finally:
         L.set_sweep_shape(0, 0, -1, 0, 5, -1)
+
+
+def test_packed_kernel_bounds():
+    """The packed 16-bit kernel at the edge of its range: a column with sum |M_xy|
+    = 2^15 - 1 (every reachable column sum fits 16 bits offset by 2^15) is taken,
+    2^15 is not; for L_marg the linear column 0 carries an offset of half its bound
+    (ceil(B_0 / 2)), so it is taken up to B_0 = 21844.  Values stay the oracle's
+    at the extremes, where some sign vectors reach column sums of +-(2^15 - 1)."""
+    say("packed bounds")
+    try:
+        L.set_sweep_shape(0, 0, -1, 0, 16, -1)
+        key = synth.stream_key(31, "edge")
+        for n, m in [(9, 10), (14, 21), (18, 34)]:      # n <= m: L1 is not transposed
+            sg = np.where(synth.uniform_ints(key, n * m, 0, 1) == 0, -1, 1).reshape(n, m)
+            mag = synth.uniform_ints(synth.stream_key(n, "mag"), n * m, 1, 50).reshape(n, m)
+            for target, packed in [(32767, True), (32768, False)]:
+                A = (sg * mag).astype(np.int64)
+                # scale column 3 so that sum |A_x3| is exactly `target`
+                col = np.abs(A[:, 3])
+                A[:, 3] = sg[:, 3] * (col * (target // col.sum()))
+                A[0, 3] += sg[0, 3] * (target - np.abs(A[:, 3]).sum())
+                assert np.abs(A[:, 3]).sum() == target
+                A = A.astype(np.int32)
+                for d in (1, 2):
+                    p = L.plan(A, d, 0)
+                    assert p["kernel"] == (5 if packed else 1), (target, d, p)
+                    check(A, d, 0)
+        # L_marg: column 0 is linear; its bound with the offset
+        for b0, packed in [(21844, True), (21845, False)]:
+            A = synth.matrix(77, 12, 16, -60, 60, "medge").astype(np.int64)
+            A[:, 0] = np.abs(A[:, 0])
+            A[:, 0] = A[:, 0] * (b0 // A[:, 0].sum())
+            A[1, 0] += b0 - A[:, 0].sum()
+            A[2, 0] = -A[2, 0]
+            assert np.abs(A[:, 0]).sum() == b0
+            A = A.astype(np.int32)
+            p = L.plan(A, 1, 1)
+            assert p["kernel"] == (5 if packed else 1), (b0, p)
+            check(A, 1, 1)
+            check(-A, 1, 1)
+        # a linear column whose values are all negative: the score is negative
+        N = -np.abs(synth.matrix(78, 9, 12, 1, 40, "neg"))
+        assert L.plan(N, 1, 1)["kernel"] == 5
+        check(N, 1, 1)
+    finally:
+        L.set_sweep_shape(0, 0, -1, 0, 5, -1)
+        L.load_tuning(L.TUNING_PATH)
 
 
 # ---------------------------------------------------------------------------
@@ -320,6 +370,62 @@ def test_range_dary(d):
     assert max(parts) == oracle.ld(M, d)
 
 
+def _dary_high_cases(d):
+    """Matrices for alphabet d with more rows than messages (else the value is
+    sum |M| without a search), sized for the oracle's class walk (about Bell(n)
+    assignments).  With two restricted-growth prefix rows the plans walk at least
+    two mid rows with the d-ary Gray code."""
+    n = d + 1 if d >= 9 else d + 2
+    ms = [5, 3] if d <= 10 else [3]
+    cases = [synth.matrix(7000 + 37 * d + i, n, m, -300, 300, "dhi") for i, m in enumerate(ms)]
+    if d == 9:
+        cases.append(synth.matrix(7200, n, 70, -300, 300, "dhi"))   # more than 64 columns too
+    return cases
+
+
+@pytest.mark.parametrize("d", [5, 6, 7, 8, 9, 10, 12])
+def test_dary_high_alphabets(d):
+    """d >= 5: the d-ary reflected Gray code (Eqs. N_ary_G1-G3, d_aryGrayChange_1)
+    over at least two mid rows, in the register kernels (d <= 8) and the wide LDS
+    kernel (d >= 9, or more than 64 columns), plain and batched, against the
+    oracle's walk over one assignment per relabelling class."""
+    say("dary high alphabets", d)
+    probs, want = [], []
+    try:
+        L.set_sweep_shape(0, 0, -1, 2, -1, -1)
+        for M in _dary_high_cases(d):
+            p = L.plan(M, d, 0)
+            assert p["kind_name"] == "L_d" and p["C"] >= 2, p
+            assert p["kernel"] == (4 if (d > 8 or M.shape[1] > 64) else 0), p
+            w = oracle.ld_classes(M, d)
+            check(M, d, 0, w)
+            probs.append((M, d, 0))
+            want.append(w)
+        assert list(L.ld_norm_batch(probs)) == want
+    finally:
+        L.set_sweep_shape(0, 0, -1, 8, -1, -1)
+
+
+@pytest.mark.parametrize("d", [13, 17, 20])
+def test_dary_range_large_alphabets(d):
+    """Alphabets beyond the restricted-growth table (d > 16 fixes row 0 only) are
+    checked on prefix sub-ranges: two free rows walk the d-ary Gray code in the
+    wide kernel, the other rows are fixed by the prefix."""
+    say("dary range d", d)
+    n, m, q = 8, 4, 5
+    M = synth.matrix(7300 + d, n, m, -300, 300, "dhr")
+    key = synth.stream_key(d, "dhr_pfx")
+    for p in [0, d ** q - 1] + [int(x) for x in synth.uniform_ints(key, 3, 0, d ** q - 1)]:
+        assert L.ld_norm_range(M, d, 0, q, p, p + 1) == oracle.range_max(M, d, 0, q, p, p + 1), p
+    assert L.ld_norm_range(M, d, 0, q, 7, 7 + 3 * d) == oracle.range_max(M, d, 0, q, 7, 7 + 3 * d)
+    # a whole problem with more rows than messages has at least d^(d-1) classes
+    # (d > 16: above 2^62, refused); with at most d rows it is sum |M|
+    p = L.plan(synth.matrix(7400 + d, d + 2, m, -300, 300, "dhr"), d, 0)
+    assert p["status"] == (L.LD_ETOOBIG if d > 16 else L.LD_OK), p
+    S = synth.matrix(7500 + d, d, m, -300, 300, "dhr")
+    assert L.ld_norm(S, d, 0) == int(np.abs(S).sum())       # the closed form for d >= rows
+
+
 def test_batch_matches_plain():
     say("batch vs plain")
     probs = []
@@ -334,10 +440,12 @@ def test_batch_matches_plain():
 
 
 def test_autotune_writes_table_and_keeps_values(tmp_path):
-    """A short autotuner run writes its table; whatever it picks, values stay equal."""
+    """A short autotuner run writes its table; whatever it picks, values stay the
+    oracle's."""
     say("autotune")
     probs = [(synth.matrix(990 + i, 10 + i % 7, 12 + i % 9, -99, 99, "tune"), 1 + i % 3, 0) for i in range(12)]
-    before = [L.ld_norm(M, d, marg) for M, d, marg in probs]
+    before = [oracle.norm(M, d, marg) for M, d, marg in probs]
+    assert [L.ld_norm(M, d, marg) for M, d, marg in probs] == before
     path = str(tmp_path / "tuning.json")
     try:
         L.autotune(path, 2.0)

@@ -481,3 +481,51 @@ def test_range_partition(d, marg):
         v = oracle.value_of(M, d, marg, a)
         best = v if best is None else max(best, v)
     assert parts[p] == best
+
+
+# ---------------------------------------------------------------------------
+# one assignment per relabelling class (Sec. 2.3.2: the value does not depend on
+# how the messages are named)
+
+
+def _stirling2_row(n):
+    """S(n, k) for k = 0..n by the textbook recurrence S(n, k) = k S(n-1, k) + S(n-1, k-1)."""
+    row = [1]
+    for i in range(1, n + 1):
+        new = [0] * (i + 1)
+        for k in range(1, i + 1):
+            new[k] = k * (row[k] if k < len(row) else 0) + row[k - 1]
+        row = new
+    return row
+
+
+@pytest.mark.parametrize("n,d", [(1, 2), (4, 2), (5, 3), (7, 3), (8, 4), (9, 9), (10, 4), (11, 12), (6, 20)])
+def test_class_count_is_stirling(n, d):
+    assert oracle.rgs_count(n, d) == sum(_stirling2_row(n)[1:d + 1])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_ld_classes_agrees(seed):
+    d = 2 + seed % 5
+    n = 2 + seed % 7
+    m = 1 + (seed * 3) % 6
+    M = rnd(seed + 500, n, m, -40, 40)
+    v = oracle.ld(M, d)
+    assert oracle.ld_classes(M, d) == v
+    assert oracle.ld_classes(M, d, 3) == v
+    if d ** n <= 2e6:
+        assert oracle.ld_all(M, d) == v
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_ld_classes_planted(d):
+    """The planted-grouping matrix of test_ld_split_planted_maximum: its maximum is
+    the planted grouping (up to relabelling), which the class walk must reach."""
+    n, m, K = 9, 8, 200
+    H = np.array([[1]], dtype=np.int64)
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    t = np.array([(x * 5 + 3) % d for x in range(n)])
+    M = (K * H[t] + rnd(d + 90, n, m, -2, 2)).astype(np.int32)
+    want = int(sum(np.abs(M[t == k].astype(np.int64).sum(axis=0)).sum() for k in range(d)))
+    assert oracle.ld_classes(M, d) == want
