@@ -254,6 +254,30 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
 int ld_autotune(const char* path, double budget_seconds);
 int ld_load_tuning(const char* path);
 
+/* Measurement aid for the int32 VALU roofline (not part of the search).  Runs a
+ * kernel on the current device in which every wave issues a known number of
+ * v_sad_u32 (the scoring instruction of the sweeps) in independent chains, four
+ * waves per SIMD, for about target_ms, and reports:
+ *   sclk_hz              engine clock under that load: the shader-clock counter
+ *                        (s_memtime) against the constant-rate counter
+ *                        (s_memrealtime, hipDeviceAttributeWallClockRate), median
+ *                        over waves;
+ *   sclk_max_hz          hipDeviceProp_t::clockRate (the rated peak clock);
+ *   valu_lane_ops_per_s  lane-instructions issued per second over the launch
+ *                        (kernel time from HIP events);
+ *   compute_units, waves, seconds.
+ * Returns 0, LD_EINVAL (null out, target_ms <= 0) or LD_EHIP (no gfx950 device,
+ * or a HIP error).  Allocates and frees a small device buffer and a stream. */
+typedef struct {
+    double sclk_hz;
+    double sclk_max_hz;
+    double valu_lane_ops_per_s;
+    double seconds;
+    int32_t compute_units;
+    int32_t waves;
+} ld_valu_probe_result;
+int ld_valu_probe(double target_ms, ld_valu_probe_result* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,12 @@ class ld_server_config(ctypes.Structure):
                 ("express_ms", ctypes.c_double)]
 
 
+class ld_valu_probe_result(ctypes.Structure):
+    _fields_ = [("sclk_hz", ctypes.c_double), ("sclk_max_hz", ctypes.c_double),
+                ("valu_lane_ops_per_s", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("compute_units", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
 class ld_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64),
@@ -91,6 +97,7 @@ SIGNATURES = {
     "ld_server_destroy": (None, [_P]),
     "ld_autotune": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double]),
     "ld_load_tuning": (ctypes.c_int, [ctypes.c_char_p]),
+    "ld_valu_probe": (ctypes.c_int, [ctypes.c_double, _P]),
 }
 
 _lib = None
@@ -321,6 +328,16 @@ def load_tuning(path: str) -> None:
     rc = lib().ld_load_tuning(path.encode())
     if rc != LD_OK:
         raise _err(rc)
+
+
+def valu_probe(target_ms: float = 200.0) -> dict:
+    """Engine clock under a VALU-bound load and the VALU issue rate the device
+    sustains (ld_valu_probe)."""
+    r = ld_valu_probe_result()
+    rc = lib().ld_valu_probe(float(target_ms), ctypes.byref(r))
+    if rc != LD_OK:
+        raise _err(rc)
+    return {f[0]: getattr(r, f[0]) for f in ld_valu_probe_result._fields_}
 
 
 class Server:

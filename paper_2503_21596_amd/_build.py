@@ -28,6 +28,7 @@ UNITS = [
     ("ld_kernels_mfma.hip", ["-DLD_KIND=2"], "kmfma2.o"),
     ("ld_kernels_dary.hip", [], "kdary.o"),
     ("ld_kernels_dary_s.hip", [], "kdarys.o"),
+    ("ld_kernels_probe.hip", [], "kprobe.o"),
     ("ld_plan.cpp", [], "plan.o"),
     ("ld_program.cpp", [], "program.o"),
     ("ld_api.cpp", [], "api.o"),

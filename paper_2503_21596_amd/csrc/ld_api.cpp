@@ -340,4 +340,71 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
     set_shape(s);
 }
 
+int ld_valu_probe(double target_ms, ld_valu_probe_result* out)
+{
+    if (!out || !(target_ms > 0)) {
+        set_error(LD_EINVAL);
+        return LD_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    int dev = 0, wall_khz = 0;
+    hipDeviceProp_t prop;
+    if (!device_ok(&dev) || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0) {
+        (void)hipGetLastError();
+        set_error(LD_EHIP);
+        return LD_EHIP;
+    }
+    // four blocks of four waves per CU: four waves per SIMD
+    const uint32_t blocks = 4u * (uint32_t)prop.multiProcessorCount, threads = 256;
+    const uint32_t waves = blocks * threads / 64;
+    uint64_t* d_out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipMalloc((void**)&d_out, 24 * (size_t)waves) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    float ms = 0;
+    uint32_t iters = 256;
+    auto launch = [&](uint32_t it) {
+        uint32_t seed = 12345u;
+        void* args[] = {(void*)&it, (void*)&seed, (void*)&d_out};
+        bool k = hipEventRecord(e0, s) == hipSuccess;
+        k = k && hipLaunchKernel(kernel_valu_probe(), dim3(blocks), dim3(threads), args, 0, s) == hipSuccess;
+        k = k && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+        return k && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    };
+    // a short launch sizes the measured one
+    ok = ok && launch(iters);
+    if (ok) {
+        const double scale = target_ms / std::max(0.01, (double)ms);
+        iters = (uint32_t)std::min(4.0e8, std::max(256.0, iters * scale));
+        ok = launch(iters);
+    }
+    std::vector<uint64_t> h(3 * (size_t)waves);
+    ok = ok && hipMemcpy(h.data(), d_out, 24 * (size_t)waves, hipMemcpyDeviceToHost) == hipSuccess;
+    if (ok) {
+        std::vector<double> clk;
+        for (uint32_t w = 0; w < waves; ++w)
+            if (h[3 * w + 1]) clk.push_back((double)h[3 * w] * wall_khz * 1e3 / (double)h[3 * w + 1]);
+        std::sort(clk.begin(), clk.end());
+        out->sclk_hz = clk.empty() ? 0.0 : clk[clk.size() / 2];
+        out->sclk_max_hz = 1e3 * (double)prop.clockRate;
+        out->seconds = ms * 1e-3;
+        out->valu_lane_ops_per_s = (double)waves * iters * 64.0 * 64.0 / (ms * 1e-3);
+        out->compute_units = prop.multiProcessorCount;
+        out->waves = (int32_t)waves;
+    }
+    if (d_out) (void)hipFree(d_out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (!ok) {
+        (void)hipGetLastError();
+        set_error(LD_EHIP);
+        return LD_EHIP;
+    }
+    return LD_OK;
+}
+
 }  // extern "C"

@@ -465,7 +465,12 @@ void choose_binary_shape(Plan& p, const SweepShape& sh, int F)
         P = std::max(P, 0);
         C = Fp - P;
         if (C < sh.c_min) {
-            C = std::min(Fp, sh.c_min);
+            // mid rows amortise a lane's start, but a small problem takes lanes
+            // first: it keeps at least 2^p_fill of them (one wave per SIMD at
+            // 2^16), and only rows beyond those become mid rows, up to c_min
+            int want = sh.c_min;
+            if (sh.p_fill > 0) want = std::min(want, Fp - sh.p_fill);
+            C = std::min(Fp, std::max(C, want));
             P = Fp - C;
         }
     }

@@ -18,7 +18,8 @@ struct SweepShape {
     int p_target = 20;   // at most this many high rows (2^20 lanes) for a binary problem
     int p_min = 19;      // at least this many, when the problem has them
     int c_goal = 12;     // between the two: aim for 2^c_goal words per prefix
-    int c_min = 4;       // least mid rows per lane when the problem allows it
+    int c_min = 4;       // least mid rows per lane when the problem allows it ...
+    int p_fill = 16;     // ... and still keeps 2^p_fill prefixes (lanes); 0: c_min always
     int r_drop = 0;      // 1: one low row fewer than the register budget allows
     int dary_ptab = 8;   // restricted-growth prefix rows for d >= 3
     int dary_cwords = 4096;  // target d^C words per lane for d >= 3

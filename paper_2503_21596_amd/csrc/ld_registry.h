@@ -68,6 +68,7 @@ const void* kernel_reset_slots();
 const void* kernel_first_equal();
 const void* kernel_set_u64();
 const void* kernel_signs();
+const void* kernel_valu_probe();   // clock and VALU-rate probe (ld_valu_probe)
 constexpr size_t WIDE_LDS_MAX = 64 * 1024;   // bytes of state per wave
 
 // padded column count used for a problem with m columns

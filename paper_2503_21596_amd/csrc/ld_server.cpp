@@ -76,7 +76,7 @@ struct Request {
     std::vector<double> cost;
     size_t next = 0;                 // first item not yet issued
     double remaining = 0;            // estimated cost of the items not yet issued
-    uint32_t outstanding = 0;        // issued items whose step has not retired
+    uint32_t outstanding = 0;        // issued items, plus the admission, whose step has not retired
     bool canceled = false;
     bool is_sum = false;
     int lane = 0;                    // 0 bulk, 1 express
@@ -282,6 +282,10 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
             r->slot = S->free_slots.back();
             S->free_slots.pop_back();
             S->slots[r->slot] = r;
+            // the admitting step writes the slot's descriptor, tables and counters:
+            // hold the slot until that step retires, even if it runs none of the
+            // request's items (a cancel meanwhile must not hand the slot on)
+            r->outstanding += 1;
             admitted.push_back(r);
         }
         // 3. items: smallest remaining work first, up to the step budget
@@ -478,6 +482,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     {
         std::lock_guard<std::mutex> g(S->mu);
         for (auto& [r, items] : picks) st.issued.push_back({r, r->is_sum ? 1u : (uint32_t)items.size()});
+        for (Request* r : admitted) st.issued.push_back({r, 1u});   // the admission hold
         S->st_launches += groups.size() + (sums.empty() ? 0 : 1);
         S->st_items += n_items;
     }

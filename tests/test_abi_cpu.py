@@ -264,7 +264,7 @@ def test_plan_kernel_family_and_mfma_selection():
         big = synth.matrix(4, 20, 20, -1000, 1000, "abi")      # deltas 2 * 1000 do not fit int8
         p = L.plan(big, 1, 0)
         assert p["kernel"] == 1 and p["R"] == 5
-        assert L.plan(synth.matrix(5, 20, 20, -120, 120, "abi"), 2, 0)["kernel"] == 2
+        assert L.plan(synth.matrix(5, 26, 26, -120, 120, "abi"), 2, 0)["kernel"] == 2
         assert L.plan(synth.matrix(6, 12, 20, -9, 9, "abi"), 3, 0)["kernel"] in (0, 1)   # d >= 3: d-ary
         assert L.plan(synth.matrix(7, 3, 70, 1, 9, "abi"), 1, 0)["kernel"] == 4          # > 64 columns: wide
     finally:
@@ -297,3 +297,19 @@ def test_error_strings_cover_every_code(lib):
     assert fallback == "unknown error code"
     assert fallback not in texts.values(), texts
     assert len(set(texts.values())) == 9
+
+
+def test_small_problems_take_lanes_before_mid_rows():
+    """A small binary problem keeps 2^16 prefixes (one wave per SIMD) before any row
+    becomes a mid row; mid rows beyond those go up to the usual minimum of four,
+    and large problems keep their shape."""
+    p = L.plan(synth.config_pm(0), 2, 0)              # 16 x 32 L2: every free row is a lane row
+    assert p["R"] == 5 and p["C"] == 0 and p["P"] == 10, p
+    p = L.plan(synth.config_pm24(0), 2, 0)            # 24 x 24 L2: 2^16 lanes, two mid rows
+    assert p["R"] == 5 and p["C"] == 2 and p["P"] == 16, p
+    p = L.plan(synth.config_small_l1(0), 1, 0)        # 20 x 20 L1
+    assert p["C"] == 0 and p["P"] == 14, p
+    p = L.plan(synth.matrix(3, 27, 27, -100, 100, "fill"), 1, 0)
+    assert p["C"] == 4 and p["P"] == 17, p
+    p = L.plan(synth.config_42_l1(0), 1, 0)
+    assert p["C"] == 16 and p["P"] == 20, p

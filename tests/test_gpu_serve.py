@@ -126,3 +126,47 @@ def test_serve_backpressure():
             if rc == L.LD_OK:
                 assert S.wait(t) == want
         assert S.stats()["rejected"] == rcs.count(L.LD_EBUSY)
+
+
+def test_serve_cancel_after_admission():
+    """Requests admitted by a bulk step that runs none of their items, cancelled at
+    once, while express requests arrive: the cancelled requests keep their slots
+    until the admitting step retires (that step still writes their descriptors and
+    counters), so no express request is handed such a slot meanwhile.  Every
+    express value is the oracle's, and a cancelled request ends either cancelled
+    or with the oracle's value."""
+    say("serve cancel after admission")
+    big = synth.matrix(11, 34, 36, -100, 100, "adm_big")          # items of 2^26 words: ~65 ms each
+    mids = [synth.matrix(300 + i, 23, 30, -100, 100, "adm_mid") for i in range(24)]
+    smalls = small_mix(6, 60)
+    want_small = [oracle.norm(A, d, marg) for A, d, marg in smalls]
+    # tiny steps (a few mid requests each), express below 2 us of estimated work
+    with L.Server(step_ms=0.01, express_ms=0.002, words_per_item=float(1 << 26)) as S:
+        t_big = S.submit(big, 1, 0)
+        time.sleep(0.005)                       # the first bulk step (one long item) runs
+        tm = [S.submit(A, 1, 0) for A in mids]  # 25 live bulk requests: a second step queues behind it
+        t0 = time.perf_counter()
+        while S.stats()["inflight"] < 1 + len(mids) and time.perf_counter() - t0 < 2.0:
+            time.sleep(0.0002)
+        admitted = S.stats()["inflight"]
+        for t in tm:
+            S.cancel(t)
+        held = S.stats()["inflight"]
+        ts = []
+        for i, (A, d, marg) in enumerate(smalls):
+            ts.append(S.submit(A, d, marg))
+            if i % 10 == 9:
+                time.sleep(0.001)
+        got = [S.wait(t) for t in ts]
+        assert got == want_small
+        for A, t in zip(mids, tm):
+            rc, v = S.wait(t, check=False)
+            assert rc in (L.LD_OK, L.LD_ECANCELED), rc
+            if rc == L.LD_OK:
+                assert v == oracle.norm(A, 1, 0)
+        S.cancel(t_big)
+        rc, _ = S.wait(t_big, check=False)
+        assert rc in (L.LD_OK, L.LD_ECANCELED)
+    # every mid request was admitted by the queued step and none was released early
+    assert admitted == 1 + len(mids), admitted
+    assert held == admitted, (held, admitted)
