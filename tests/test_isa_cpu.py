@@ -221,3 +221,111 @@ def test_dary_gray_loop_has_no_spills(tmp_path):
     spills = gray_loop_spills(open(tmp_path / listing[0]).read().splitlines())
     assert len(spills) == 23, sorted(spills)   # d = 3: 4 .. 52 columns, d = 4: 4 .. 40
     assert all(v == 0 for v in spills.values()), {k: v for k, v in spills.items() if v}
+
+
+# ---------------------------------------------------------------------------
+# 4. Queue pops: every wave takes its next item index from a returning atomic
+# and broadcasts it with v_readfirstlane.  That is only sound when the lane that
+# v_readfirstlane reads is the lane that performed the atomic.  The compiler's own
+# atomic optimizer guarantees it: it guards the atomic with "first active lane"
+# (v_mbcnt of exec compared with 0) and broadcasts after restoring the same exec.
+# A hand-written "lane 0 only" guard does not: if the wave reaches that code with
+# lane 0 inactive, v_readfirstlane reads a lane that never performed the atomic
+# (a stale index), and the wave can loop forever.  The scan flags every returning
+# atomic whose result reaches v_readfirstlane under a guard other than the
+# first-active-lane one, or with exec narrowed further in between.
+
+RET_ATOMIC = re.compile(r"\s+(global|flat|buffer)_atomic_\w+\s+v(\d+)(?:,|\s).*\bsc0\b")
+READFIRST = re.compile(r"\s+v_readfirstlane_b32\s+s\d+,\s+v(\d+)\b")
+SAVEEXEC = re.compile(r"\s+s_and_saveexec_b64\s+s\[(\d+):(\d+)\],\s+vcc")
+RESTORE = re.compile(r"\s+s_or_b64\s+exec,\s+exec,\s+s\[(\d+):(\d+)\]")
+CMP_LANE0 = re.compile(r"\s+v_cmp_eq_u32_e32\s+vcc,\s+0,\s+v(\d+)\b")
+VDST = re.compile(r"\s+(v_\w+)\s+v(\d+),")
+
+
+def unsafe_broadcasts(lines, checked=None):
+    """(function, line) of v_readfirstlane reads of a returning atomic's result
+    that are not guaranteed to read the lane that performed the atomic.  `checked`
+    (a list) receives every such broadcast found, safe or not."""
+    bad = []
+    fn = None
+    writer = {}        # VGPR -> opcode that last wrote it
+    guard_src = None   # kind of the last vcc = (v == 0) compare: "first" or "other"
+    stack = []         # open exec-narrowing regions: (saved sgpr pair, kind)
+    atom = {}          # VGPR -> (kind of the innermost guard, depth of the stack) at the atomic
+    for line in lines:
+        f = FUNC.match(line)
+        if f:
+            fn, writer, guard_src, stack, atom = f.group(1), {}, None, [], {}
+            continue
+        s = line.split("//")[0]
+        m = CMP_LANE0.match(s)
+        if m:
+            guard_src = "first" if writer.get(int(m.group(1))) == "v_mbcnt_hi_u32_b32" else "other"
+        elif "vcc" in s.split(",")[0] and s.strip().startswith("v_cmp"):
+            guard_src = "other"
+        m = SAVEEXEC.match(s)
+        if m:
+            stack.append((m.group(1), guard_src or "other"))
+            continue
+        m = RESTORE.match(s)
+        if m:
+            for i in range(len(stack) - 1, -1, -1):
+                if stack[i][0] == m.group(1):
+                    del stack[i:]
+                    break
+            continue
+        m = RET_ATOMIC.match(s)
+        if m:
+            atom[int(m.group(2))] = (stack[-1][1] if stack else "none", len(stack))
+            continue
+        m = READFIRST.match(s)
+        if m and int(m.group(1)) in atom:
+            kind, depth = atom.pop(int(m.group(1)))
+            if checked is not None:
+                checked.append((fn, kind))
+            if kind == "other" or (kind == "first" and len(stack) != depth - 1) or \
+                    (kind == "none" and len(stack) != depth):
+                bad.append((fn, s.strip()))
+            continue
+        m = VDST.match(s)
+        if m:
+            writer[int(m.group(2))] = m.group(1)
+            atom.pop(int(m.group(2)), None)
+    return bad
+
+
+def test_broadcast_scan_catches_a_lane0_guard():
+    """The pattern of a lane-0-only pop (the compiler may re-enter the loop with
+    lane 0 inactive) is flagged; the atomic optimizer's first-active-lane form is
+    not."""
+    bad = ["0000000000000000 <k>:",
+           "\tv_and_b32_e32 v7, 63, v0",
+           "\tv_cmp_eq_u32_e32 vcc, 0, v7",
+           "\ts_and_saveexec_b64 s[0:1], vcc",
+           "\tglobal_atomic_add v2, v1, v2, s[4:5] sc0",
+           "\ts_or_b64 exec, exec, s[0:1]",
+           "\ts_waitcnt vmcnt(0)",
+           "\tv_readfirstlane_b32 s0, v2"]
+    assert len(unsafe_broadcasts(bad)) == 1
+    good = list(bad)
+    good[1:2] = ["\tv_mbcnt_lo_u32_b32 v7, exec_lo, 0", "\tv_mbcnt_hi_u32_b32 v7, exec_hi, v7"]
+    assert unsafe_broadcasts(good) == []
+    # exec narrowed again before the broadcast
+    worse = good[:-1] + ["\tv_cmp_gt_u32_e32 vcc, 5, v9", "\ts_and_saveexec_b64 s[8:9], vcc", good[-1]]
+    assert len(unsafe_broadcasts(worse)) == 1
+
+
+@pytest.mark.parametrize("obj", ["kbin0.o", "kbin1.o", "kbin2.o", "kdary.o", "kdarys.o", "kmfma0.o", "kmfma1.o",
+                                 "kmfma2.o"])
+def test_queue_pops_broadcast_the_atomic_lane(obj, tmp_path):
+    path = os.path.join(BUILD, obj)
+    if not os.path.exists(path):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    if not os.path.exists(f"{LLVM}/llvm-objdump"):
+        pytest.skip("ROCm LLVM tools not found")
+    lines = _disassemble(path, tmp_path)
+    checked = []
+    bad = unsafe_broadcasts(lines, checked)
+    assert len(checked) > 40, len(checked)      # every queue kernel pops through one
+    assert not bad, bad[:5]
