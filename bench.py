@@ -22,8 +22,20 @@ METRIC = "Gray-code steps/s (% INT32 VALU peak); 42×42 L1 secs; batched vs plai
 
 
 def alg_ops_per_word(kind: str, m: int) -> int:
-    """Irreducible int32 VALU work to score one word: one fused |.|-accumulate per
-    column (per column and message side for L2), plus the running max."""
+    """Algorithmic int32 VALU work per Gray step of the paper's method (one row update
+    and one fused |.|-accumulate per column, plus the running max): 2m + 1 for L1 and
+    L_marg, 3m + 1 for L2 (Eq. update, Eq. LM2)."""
+    if kind in ("L1", "L_marg"):
+        return 2 * m + 1
+    if kind == "L2":
+        return 3 * m + 1
+    raise ValueError(kind)
+
+
+def scoring_ops_per_word(kind: str, m: int) -> int:
+    """The scoring part alone: one |.|-accumulate per column (two for L2) and the max.
+    The kernels share one row update among 2^R low-row patterns, so with one column
+    per instruction this is the count they cannot go below."""
     if kind in ("L1", "L_marg"):
         return m + 1
     if kind == "L2":
@@ -32,25 +44,26 @@ def alg_ops_per_word(kind: str, m: int) -> int:
 
 
 KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip"]
-TRAFFIC_PROFILE = "profiles/k_bin32s_l1_42x42.md"
+HEADLINE_PROFILE = "profiles/k_bin16s_l1_42x42.md"
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the sweep kernel from the committed rocprofv3 summary,
-    or None when the kernel sources changed after the counters were taken."""
+def profile_fields(path: str = HEADLINE_PROFILE) -> dict:
+    """The `key: value` lines of a committed rocprofv3 summary, or {} when the kernel
+    sources changed after the profile was taken (its counters then describe another
+    kernel)."""
     import hashlib
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
-        return None
+        return {}
     fields = {}
     for line in open(path):
-        if ":" in line and not line.startswith(("|", " ", "#")):
+        if ":" in line and not line.startswith(("|", " ", "#", "-")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
-    if fields.get("kernel_source_sha256_16") != h[:16] or "traffic_bytes" not in fields:
-        return None
-    return float(fields["traffic_bytes"])
+    if fields.get("kernel_source_sha256_16") != h[:16]:
+        return {}
+    return fields
 
 
 def cpu_baseline(M, target_s: float = 15.0):
@@ -292,7 +305,23 @@ def main():
     steps_per_s = words * a.steps / (total_ms / 1e3)
     kavg = sum(kernel_ms) / len(kernel_ms)
     ops = alg_ops_per_word("L1", plan["m"])
+    sops = scoring_ops_per_word("L1", plan["m"])
     achieved = words * ops / (kavg / 1e3)
+    # engine clock under a VALU-bound load, and the issue rate the chip sustains
+    probe = L.valu_probe(200.0)
+    prof = profile_fields()
+    valu_issue = None
+    if prof.get("valu_insts_per_launch") and probe["sclk_hz"] > 0:
+        # wave-level VALU instructions of the profiled launch against the issue
+        # capacity of this launch (one wave64 instruction per SIMD per 4 clocks,
+        # 4 SIMDs per CU) at the measured clock
+        valu_issue = float(prof["valu_insts_per_launch"]) / (kavg / 1e3 * probe["compute_units"] * probe["sclk_hz"])
+    packed = plan["kernel"] == 5
+    note = ("frac counts the paper's per-step work, 2m + 1 int32 ops (row update, one |.|-accumulate per "
+            "column, max); it exceeds 1 because the kernel shares one row update among 2^R = %d low-row "
+            "patterns%s. valu_issue_frac (profiled instruction count over issue capacity at the measured "
+            "clock) is the hardware utilisation." %
+            (1 << plan["R"], " and scores two columns per v_sad_u16 (16-bit halves)" if packed else ""))
 
     golden = None
     gpath = os.path.join(ROOT, "tests", "golden", "configs_seed0.json")
@@ -318,12 +347,22 @@ def main():
                    "plan": {k: plan[k] for k in ("mp", "R", "C", "P", "n_prefix", "i64", "kernel")}},
         "l1_42_seconds": ms_per_step / 1e3,
         "pct_int32_valu_peak": 100.0 * achieved / INT32_VALU_PEAK,
+        "pct_int32_valu_issue": 100.0 * valu_issue if valu_issue else None,
         "result": value,
         "matches_oracle": (value == golden) if golden is not None else None,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_VALU_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU)", "frac": achieved / INT32_VALU_PEAK,
-                     "traffic": profiled_traffic(),
-                     "ops_per_step": ops, "kernel_ms": kavg},
+                     "traffic": float(prof["traffic_bytes"]) if "traffic_bytes" in prof else None,
+                     "ops_per_step": ops, "note": note,
+                     "scoring_ops_per_step": sops,
+                     "frac_scoring_only": words * sops / (kavg / 1e3) / INT32_VALU_PEAK,
+                     "valu_insts_per_step": (float(prof["valu_insts_per_launch"]) / words
+                                             if prof.get("valu_insts_per_launch") else None),
+                     "valu_issue_frac": valu_issue,
+                     "sclk_measured_hz": probe["sclk_hz"], "sclk_rated_hz": probe["sclk_max_hz"],
+                     "peak_at_measured_clock": probe["compute_units"] * 64 * probe["sclk_hz"] / 1e12,
+                     "probe_valu_frac": probe["valu_lane_ops_per_s"] / INT32_VALU_PEAK,
+                     "kernel_ms": kavg, "profile": HEADLINE_PROFILE if prof else None},
         "wall_s": wall,
     }
 

@@ -244,6 +244,20 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
 void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r,
                         int32_t dary_sgpr);
 
+/* Lane floor of small binary problems for new plans: a problem with few free rows
+ * keeps at least 2^p_fill prefixes (lanes) before rows become mid rows (up to the
+ * c_min of ld_set_sweep_shape); p_fill = 0 turns the floor off, so such problems
+ * take c_min mid rows whenever they have them.  The default is 16 (one wave per
+ * SIMD).  Negative values are ignored.  Values never depend on it. */
+void ld_set_lane_fill(int32_t p_fill);
+
+/* Resident waves per SIMD of the sweep launches of plain and batch calls made from
+ * now on (the paper's total-thread-count question, Sec. 4): the persistent queue
+ * kernels launch at most waves_per_simd x 4 x CUs waves.  0 (the default) launches
+ * as many as the kernel's occupancy allows; negative values are ignored.  Batches
+ * prepared earlier keep the launches they captured.  Values never depend on it. */
+void ld_set_launch_waves(int32_t waves_per_simd);
+
 /* Autotuner.  The paper found no general rule for the launch shape and advises
  * timing a smaller matrix first (Sec. 4).  ld_autotune times candidate shapes on
  * the current device -- words per prefix and per queue item for batches, lane

@@ -79,6 +79,8 @@ SIGNATURES = {
     "ld_gray_digit": (_U32, [_U32, _U32, _U64]),
     "ld_gray_change": (_I32, [_U32, _U64, _P, _P]),
     "ld_set_sweep_shape": (None, [_I32, _I32, _I32, _I32, _I32, _I32]),
+    "ld_set_lane_fill": (None, [_I32]),
+    "ld_set_launch_waves": (None, [_I32]),
     "ld_prepare": (_P, [_P, _I32, _I32, _I32, _I32]),
     "ld_run": (ctypes.c_int, [_P, _P, _P]),
     "ld_last_kernel_ms": (ctypes.c_float, [_P]),
@@ -316,6 +318,14 @@ def gray_change(d: int, j: int):
 def set_sweep_shape(p_target: int = 0, c_min: int = 0, r_drop: int = -1, dary_ptab: int = 0,
                     sgpr_r: int = -1, dary_sgpr: int = -1) -> None:
     lib().ld_set_sweep_shape(p_target, c_min, r_drop, dary_ptab, sgpr_r, dary_sgpr)
+
+
+def set_lane_fill(p_fill: int = 16) -> None:
+    lib().ld_set_lane_fill(p_fill)
+
+
+def set_launch_waves(waves_per_simd: int = 0) -> None:
+    lib().ld_set_launch_waves(waves_per_simd)
 
 
 def autotune(path: Optional[str] = None, budget_seconds: float = 20.0) -> None:

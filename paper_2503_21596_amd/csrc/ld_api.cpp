@@ -340,6 +340,19 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
     set_shape(s);
 }
 
+void ld_set_lane_fill(int32_t p_fill)
+{
+    if (p_fill < 0) return;
+    SweepShape s = get_shape();
+    s.p_fill = std::min(p_fill, 40);
+    set_shape(s);
+}
+
+void ld_set_launch_waves(int32_t waves_per_simd)
+{
+    if (waves_per_simd >= 0) set_launch_waves(std::min(waves_per_simd, 32));
+}
+
 int ld_valu_probe(double target_ms, ld_valu_probe_result* out)
 {
     if (!out || !(target_ms > 0)) {

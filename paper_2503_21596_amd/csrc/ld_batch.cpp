@@ -149,7 +149,7 @@ ld_batch* ld_batch_prepare(const ld_problem* probs, int32_t count, int32_t* stat
     }
     // occupancy queries are not stream work: make them before the capture
     if (ok)
-        for (const Launch& L : b->prog.launches) (void)resident_blocks(L.kernel, L.threads, L.lds);
+        for (const Launch& L : b->prog.launches) (void)capped_blocks(L.kernel, L.threads, L.lds);
     // capture reset + launches + result copy once; every run replays the graph
     ok = ok && hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <utility>
 
@@ -16,11 +17,6 @@ namespace ld {
 namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-int kind_of(const Plan& p)
-{
-    return p.kind == PK_L1 ? KIND_L1 : p.kind == PK_MARG ? KIND_MARG : p.kind == PK_L2 ? KIND_L2 : KIND_LD;
-}
 
 // descriptors and sum items as built: their pointers hold byte offsets into the
 // image until patch_program rebases them on a device address
@@ -193,25 +189,9 @@ Program build_program(const std::vector<const Plan*>& plans, const ItemShape& sh
         const Plan& p = *plans[i];
         if (p.kind == PK_ZERO) continue;
         std::memcpy(P.image.data() + P.blob_off[i], p.blob.data(), p.blob.size());
-        Desc D{};
-        D.kind = kind_of(p);
-        D.m = p.m;
-        D.mp = p.mp;
-        D.d = p.d;
-        D.i64 = p.i64;
-        D.R = p.R;
-        D.C = p.C;
-        D.P = p.P;
-        D.P_tab = p.P_tab;
-        D.pfx_base = p.pfx_base;
-        D.n_prefix = p.n_prefix;
-        D.dpow_free = p.dpow_free;
-        D.base = (const void*)(uintptr_t)(P.blob_off[i] + p.off_base);
-        D.hid = (const void*)(uintptr_t)(P.blob_off[i] + p.off_hid);
-        D.mid = (const void*)(uintptr_t)(P.blob_off[i] + p.off_mid);
-        D.offs = (const void*)(uintptr_t)(P.blob_off[i] + p.off_offs);
-        D.tab = (const uint64_t*)(uintptr_t)(P.blob_off[i] + p.off_tab);
-        D.result = (int64_t*)(uintptr_t)(P.off_results + 8 * (size_t)i);
+        // pointers as byte offsets into the image (rebased by patch_program)
+        Desc D = make_desc(p, (const void*)(uintptr_t)P.blob_off[i],
+                           (int64_t*)(uintptr_t)(P.off_results + 8 * (size_t)i));
         D.rec = (int64_t*)(uintptr_t)P.rec_off[i];
         rel.descs[i] = D;
     }
@@ -269,6 +249,36 @@ void patch_program(Program& P, void* dev)
     P.dev = dev;
 }
 
+namespace {
+std::atomic<int> g_launch_waves{0};   // waves per SIMD of plain and batch launches; 0: occupancy
+}  // namespace
+
+void set_launch_waves(int waves_per_simd) { g_launch_waves.store(std::max(0, waves_per_simd)); }
+
+uint32_t capped_blocks(const void* kernel, uint32_t threads, size_t lds)
+{
+    const uint32_t full = resident_blocks(kernel, threads, lds);
+    const int w = g_launch_waves.load();
+    if (w <= 0) return full;
+    // blocks of threads / 64 waves; four SIMDs per CU
+    const uint32_t cus = std::max<uint32_t>(1, device_cus());
+    const uint32_t cap = std::max<uint32_t>(1, (uint32_t)w * 4 * cus / std::max<uint32_t>(1, threads / 64));
+    return std::min(full, cap);
+}
+
+uint32_t device_cus()
+{
+    static std::atomic<uint32_t> cus{0};
+    uint32_t c = cus.load();
+    if (c) return c;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        c = (uint32_t)prop.multiProcessorCount;
+    cus.store(c);
+    return c;
+}
+
 uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds)
 {
     static std::mutex mu;
@@ -310,7 +320,7 @@ bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
         q.n_prefix = L.n_prefix;
         const uint32_t waves_per_block = L.threads / 64;
         const uint32_t want = (L.n_items + waves_per_block - 1) / waves_per_block;
-        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, resident_blocks(L.kernel, L.threads, L.lds)));
+        const uint32_t blocks = std::max<uint32_t>(1, std::min(want, capped_blocks(L.kernel, L.threads, L.lds)));
         void* args[] = {(void*)&q};
         if (hipLaunchKernel(L.kernel, dim3(blocks), dim3(L.threads), args, L.lds, s) != hipSuccess) return false;
     }

@@ -94,5 +94,10 @@ bool enqueue_program(const Program& prog, hipStream_t s, int64_t* host_results);
 
 // Blocks per launch that fill the device once for a kernel (occupancy x CUs).
 uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds);
+// The same, capped at the waves per SIMD set by set_launch_waves (plain and batch
+// launches; the server sizes its own launches).
+uint32_t capped_blocks(const void* kernel, uint32_t threads, size_t lds);
+void set_launch_waves(int waves_per_simd);   // 0: as many as occupancy allows
+uint32_t device_cus();                       // compute units of the current device
 
 }  // namespace ld

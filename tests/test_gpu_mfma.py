@@ -33,10 +33,14 @@ def say(*a):
 
 @pytest.fixture
 def mfma():
+    # small problems here keep mid rows (the kernel needs 1 <= C <= 16) instead of
+    # trading them for lanes
     L.set_sweep_shape(0, 0, -1, 0, VARIANT_MFMA, -1)
+    L.set_lane_fill(0)
     try:
         yield
     finally:
+        L.set_lane_fill(16)
         L.set_sweep_shape(20, 4, -1, 0, 5, -1)
         if os.path.exists(L.TUNING_PATH):
             L.load_tuning(L.TUNING_PATH)

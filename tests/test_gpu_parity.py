@@ -383,6 +383,19 @@ def _dary_high_cases(d):
     return cases
 
 
+def _plan_two_mid_rows(M, d):
+    """Set the fewest restricted-growth prefix rows (from 2 up) whose plan walks at
+    least two mid rows with at most 10^8 words, and return that plan; the words
+    bound keeps the wide kernel's share (one wave per prefix) to a fraction of a
+    second.  Raises on the host if no such shape exists."""
+    for ptab in (2, 4, 6, 8, 10, 12):
+        L.set_sweep_shape(0, 0, -1, ptab, -1, -1)
+        p = L.plan(M, d, 0)
+        if p["C"] >= 2 and p["words"] <= 1e8:
+            return p
+    raise AssertionError(("no plan with two mid rows and at most 1e8 words", M.shape, d))
+
+
 @pytest.mark.parametrize("d", [5, 6, 7, 8, 9, 10, 12])
 def test_dary_high_alphabets(d):
     """d >= 5: the d-ary reflected Gray code (Eqs. N_ary_G1-G3, d_aryGrayChange_1)
@@ -390,17 +403,21 @@ def test_dary_high_alphabets(d):
     kernel (d >= 9, or more than 64 columns), plain and batched, against the
     oracle's walk over one assignment per relabelling class."""
     say("dary high alphabets", d)
-    probs, want = [], []
+    probs, want, ptabs = [], [], []
     try:
-        L.set_sweep_shape(0, 0, -1, 2, -1, -1)
         for M in _dary_high_cases(d):
-            p = L.plan(M, d, 0)
+            p = _plan_two_mid_rows(M, d)
             assert p["kind_name"] == "L_d" and p["C"] >= 2, p
             assert p["kernel"] == (4 if (d > 8 or M.shape[1] > 64) else 0), p
+            say("  ", M.shape, "C", p["C"], "P_tab", p["P_tab"], "words", p["words"])
+            ptabs.append(p["P_tab"])
             w = oracle.ld_classes(M, d)
             check(M, d, 0, w)
             probs.append((M, d, 0))
             want.append(w)
+        # the batch under the largest of those prefix shapes, its size checked first
+        L.set_sweep_shape(0, 0, -1, max(ptabs), -1, -1)
+        assert all(L.plan(M, d, 0, batch=True)["words"] <= 1e8 for M, d, _ in probs)
         assert list(L.ld_norm_batch(probs)) == want
     finally:
         L.set_sweep_shape(0, 0, -1, 8, -1, -1)
