@@ -233,6 +233,85 @@ def bench_mfma_variant(L, synth, stream, default_ms, golden, tuning=""):
             "value": v, "matches_oracle": (v == golden) if golden is not None else None}
 
 
+def bench_sweep(L, synth, stream, reps: int = 3):
+    """Kernel time of one solve against the number of lanes (prefixes, one per lane)
+    and the resident waves per SIMD, for L1, L2, L_3 and L_4: the launch-shape
+    question of the paper's Sec. 4 (Fig. 3), where the best total thread count
+    followed no general rule.  Lanes: binary 2^P for P = 12 .. 22 (ld_set_sweep_shape
+    p_target); d-ary the plan's lane count for lane targets 2^12 .. 2^20 (a tuning
+    table carrying plain_dary_lanes).  Waves per SIMD 1 .. 8 at the tuned lane count
+    (ld_set_launch_waves; the kernel's occupancy caps the count)."""
+    import tempfile
+    workloads = [("L1_36x36", 1, 36, 36), ("L2_31x31", 2, 31, 31), ("L3_22x32", 3, 22, 32), ("L4_18x24", 4, 18, 24)]
+    tuned = os.path.exists(L.TUNING_PATH) and os.environ.get("LD_TUNING", "1") != "0"
+
+    def dary_lanes(n):
+        with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+            f.write('{"plain_dary_lanes": %d}' % n)
+        L.load_tuning(f.name)
+        os.unlink(f.name)
+
+    def restore():
+        L.set_launch_waves(0)
+        L.set_sweep_shape(20, 0, -1, 0, -1, -1)
+        if tuned:
+            L.load_tuning(L.TUNING_PATH)
+        else:
+            dary_lanes(1 << 19)   # the compiled default
+
+    def timed(M, d):
+        h = L.Prepared(M, d, 0)
+        v = h.run(stream)
+        ks = []
+        for _ in range(reps):
+            h.run(stream)
+            ks.append(h.kernel_ms())
+        p = h.plan()
+        h.close()
+        return {"lanes": p["n_prefix"], "C": p["C"], "R": p["R"], "kernel": p["kernel"], "ms": min(ks),
+                "words_per_s": p["words"] / (min(ks) / 1e3), "value": v}
+
+    out = {}
+    for name, d, n, m in workloads:
+        M = synth.matrix(500 + n + m + d, n, m, -100, 100, "sweep")
+        rows = []
+        try:
+            for k in range(12, 23 if d <= 2 else 21):
+                if d <= 2:
+                    L.set_sweep_shape(k, 0, -1, 0, -1, -1)
+                else:
+                    dary_lanes(1 << k)
+                r = timed(M, d)
+                r["target"] = k
+                rows.append(r)
+        finally:
+            restore()
+        waves = []
+        try:
+            for w in range(1, 9):
+                L.set_launch_waves(w)
+                r = timed(M, d)
+                r["waves_per_simd"] = w
+                waves.append(r)
+        finally:
+            restore()
+        ref = timed(M, d)
+        assert all(r["value"] == ref["value"] for r in rows + waves), name
+        best = min(rows, key=lambda r: r["ms"])
+        out[name] = {"lanes": rows, "waves": waves, "tuned": ref, "best_lanes": best["lanes"],
+                     "best_is_power_of_d": best["lanes"] & (best["lanes"] - 1) == 0 if d <= 2
+                     else _is_power(best["lanes"], d)}
+        print(f"sweep {name}: best {best['lanes']} lanes {best['ms']:.3f} ms, tuned {ref['lanes']} lanes "
+              f"{ref['ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def _is_power(x: int, b: int) -> bool:
+    while x > 1 and x % b == 0:
+        x //= b
+    return x == 1
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,11 +321,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tuning", default="", help="load this autotuner table before measuring")
     ap.add_argument("--kernel-variant", type=int, default=-1,
-                    help="binary sweep kernel for the headline solve: 5 or 4 (SGPR operands, that many "
-                         "low rows), 0 (VGPR operands), 8 (int8-MFMA state update); default: tuned")
+                    help="sweep kernel variant: 16 (packed 16-bit, binary and d-ary), 5 or 4 (binary, SGPR "
+                         "operands, that many low rows), 1 (d-ary, SGPR operands), 0 (VGPR operands), "
+                         "8 (binary, int8-MFMA state update); default: tuned")
     ap.add_argument("--solve", default="",
                     help="D,N,M: instead of the benchmark, time one solve of L_D on a seeded N x M matrix "
                          "(entries U[-100,100]) and print its plan and kernel time (for profiling)")
+    ap.add_argument("--small", action="store_true",
+                    help="instead of the benchmark, run only the smaller workloads (20x20 L1, 16x32 at d = 2, "
+                         "3, 4, 24x24 L2) and print their timings as one JSON line (for profiling)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark, time one solve each of L1, L2, L_3 and L_4 across lane "
+                         "counts and waves per SIMD and print the table as one JSON line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
                          "known traffic, to scale the HBM counters of a profiler run)")
@@ -265,6 +351,17 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.tuning:
+        L.load_tuning(a.tuning)
+    if a.kernel_variant >= 0:
+        kv = a.kernel_variant
+        L.set_sweep_shape(0, 0, -1, 0, kv if kv in (0, 4, 5, 8, 16) else -1, kv if kv in (0, 1, 16) else -1)
+    if a.sweep:
+        print(json.dumps({"sweep": bench_sweep(L, synth, stream)}), flush=True)
+        return
+    if a.small:
+        print(json.dumps({"other_configs": bench_small_configs(L, synth, stream)}), flush=True)
+        return
     if a.solve:
         d, n, m = (int(x) for x in a.solve.split(","))
         Ms = synth.matrix(91 + n + m, n, m, -100, 100, "prof")
@@ -276,10 +373,6 @@ def main():
                                                                   "n_prefix", "words")}}}), flush=True)
         hs.close()
         return
-    if a.tuning:
-        L.load_tuning(a.tuning)
-    if a.kernel_variant >= 0:
-        L.set_sweep_shape(0, 0, -1, 0, a.kernel_variant, -1)
     M = synth.config_42_l1(0)
     h = L.Prepared(M, 1, 0)
     plan = h.plan()
@@ -311,11 +404,14 @@ def main():
     probe = L.valu_probe(200.0)
     prof = profile_fields()
     valu_issue = None
-    if prof.get("valu_insts_per_launch") and probe["sclk_hz"] > 0:
+    # the kernel's own clock from the profile (busy cycles per shader engine over its
+    # time), else the probe's clock under its VALU load
+    sclk = float(prof.get("sclk_from_busy_cycles_hz", 0) or probe["sclk_hz"])
+    if prof.get("valu_insts_per_launch") and sclk > 0:
         # wave-level VALU instructions of the profiled launch against the issue
         # capacity of this launch (one wave64 instruction per SIMD per 4 clocks,
-        # 4 SIMDs per CU) at the measured clock
-        valu_issue = float(prof["valu_insts_per_launch"]) / (kavg / 1e3 * probe["compute_units"] * probe["sclk_hz"])
+        # 4 SIMDs per CU) at that clock
+        valu_issue = float(prof["valu_insts_per_launch"]) / (kavg / 1e3 * probe["compute_units"] * sclk)
     packed = plan["kernel"] == 5
     note = ("frac counts the paper's per-step work, 2m + 1 int32 ops (row update, one |.|-accumulate per "
             "column, max); it exceeds 1 because the kernel shares one row update among 2^R = %d low-row "
@@ -359,8 +455,9 @@ def main():
                      "valu_insts_per_step": (float(prof["valu_insts_per_launch"]) / words
                                              if prof.get("valu_insts_per_launch") else None),
                      "valu_issue_frac": valu_issue,
-                     "sclk_measured_hz": probe["sclk_hz"], "sclk_rated_hz": probe["sclk_max_hz"],
-                     "peak_at_measured_clock": probe["compute_units"] * 64 * probe["sclk_hz"] / 1e12,
+                     "sclk_kernel_hz": sclk, "sclk_probe_hz": probe["sclk_hz"],
+                     "sclk_rated_hz": probe["sclk_max_hz"],
+                     "peak_at_measured_clock": probe["compute_units"] * 64 * sclk / 1e12,
                      "probe_valu_frac": probe["valu_lane_ops_per_s"] / INT32_VALU_PEAK,
                      "kernel_ms": kavg, "profile": HEADLINE_PROFILE if prof else None},
         "wall_s": wall,

@@ -238,7 +238,10 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
  * as 16-bit halves (5 low rows; used where every column has sum_x |M_xy| <= 32767,
  * and for L_marg column 0 at most 21844, else the SGPR kernel with 5 low rows
  * runs); dary_sgpr: 1 for the d-ary kernel with
- * SGPR operands (d = 3, 4, three low rows) where it is built, 0 for the VGPR one.
+ * SGPR operands (d = 3, 4, three low rows) where it is built, 0 for the VGPR one,
+ * 16 for the packed 16-bit d-ary kernel (two columns per register; four low rows
+ * for d = 3, three for d = 4; used under the same column bound as the binary one,
+ * else the SGPR-operand kernel runs).  The compiled defaults are 16 for both.
  * An explicit sgpr_r or dary_sgpr also replaces the autotuner's per-width choices
  * for those kinds.  Values never depend on the shape. */
 void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t dary_ptab, int32_t sgpr_r,

@@ -333,7 +333,7 @@ void ld_set_sweep_shape(int32_t p_target, int32_t c_min, int32_t r_drop, int32_t
             for (int b = 0; b < 4; ++b) s.variant[c][b] = -1;
     }
     if (dary_sgpr >= 0) {
-        s.dary_sgpr = dary_sgpr ? 1 : 0;
+        s.dary_sgpr = dary_sgpr == VARIANT_PACK16 ? VARIANT_PACK16 : dary_sgpr ? 1 : 0;
         for (int c = 2; c < 4; ++c)
             for (int b = 0; b < 4; ++b) s.variant[c][b] = -1;
     }

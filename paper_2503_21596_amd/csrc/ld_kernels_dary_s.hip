@@ -20,12 +20,20 @@ constexpr int dary_s_waves(int mp, int d)
     return mp <= 16 ? 4 : mp <= 28 ? 3 : 2;
 }
 
-// Persistent queue kernel (see k_bin32): one item = a range of prefixes of one
-// problem, one lane per prefix.
-template <int MP, int DD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_waves(MP, DD)))) void k_dary32s(QArgs q)
+// The same for the packed 16-bit kernels, by dword count W (two columns each):
+// the d vectors of W dwords, the 2^R subset scores of each message and the
+// temporaries.
+constexpr int dary16_waves(int w, int d)
 {
-    using K = Dary32S<MP, DD, DARY_RS>;
+    if (d == 3) return w <= 20 ? 4 : 3;
+    return w <= 12 ? 4 : 3;
+}
+
+// Persistent queue kernel (see k_bin32): one item = a range of prefixes of one
+// problem, one lane per prefix.  K is the sweep (Dary32S, plain or packed).
+template <class K>
+__device__ __forceinline__ void dary_s_queue(const QArgs& q)
+{
     const uint32_t lane = threadIdx.x & 63;
     queue_priority(q);
     WaveBest wb;
@@ -49,15 +57,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_wave
     wb.flush();
 }
 
+template <int MP, int DD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_waves(MP, DD)))) void k_dary32s(QArgs q)
+{
+    dary_s_queue<Dary32S<MP, DD, DARY_RS>>(q);
+}
+
+template <int W, int DD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary16_waves(W, DD)))) void k_dary16s(QArgs q)
+{
+    dary_s_queue<Dary32S<W, DD, dary16_r(DD), true>>(q);
+}
+
 namespace {
 
 constexpr int NMPD = MAX_MP / 4;   // mp = 4, 8, ..., 64
 const void* g_dary32s[MAX_D + 1][NMPD] = {};
+const void* g_dary16s[MAX_D + 1][NMPD] = {};   // by dword count 2, 4, ..., 32
 
 template <int DD, int MP>
 void reg_one()
 {
     if constexpr (dary_s_fits(MP, DD)) g_dary32s[DD][MP / 4 - 1] = (const void*)&k_dary32s<MP, DD>;
+    if constexpr (dary16_fits(MP / 2, DD)) g_dary16s[DD][MP / 4 - 1] = (const void*)&k_dary16s<MP / 2, DD>;
 }
 
 template <int DD, int... I>
@@ -80,6 +102,12 @@ const void* kernel_dary32s(int d, int mp)
 {
     if (d < 0 || d > MAX_D || mp < 4 || mp > MAX_MP || (mp & 3)) return nullptr;
     return g_dary32s[d][mp / 4 - 1];
+}
+
+const void* kernel_dary16s(int d, int words)
+{
+    if (d < 0 || d > MAX_D || words < 2 || words > MAX_MP / 2 || (words & 1)) return nullptr;
+    return g_dary16s[d][words / 2 - 1];
 }
 
 }  // namespace ld

@@ -228,6 +228,7 @@ void put(std::vector<uint8_t>& blob, size_t off, size_t idx, T v)
 
 constexpr int64_t BIAS = (int64_t)1 << 31;
 constexpr uint64_t WORD_LIMIT = (uint64_t)1 << 62;
+constexpr double RGS_TRADE_MAX = 4096;   // restricted-growth strings a lane trade may grow the table to
 
 // Binary tables.  Row roles in A: row 0 fixed (a_0 = +1, or message 0 for L2),
 // rows 1..R low, then C mid rows, then P high rows.  A digit is the bit of the
@@ -358,40 +359,51 @@ void build_dary(Plan& p, const Mat& A, const std::vector<uint64_t>& tab, bool fi
     const int low0 = mid0 + C;
     const int NS = 1 << R;
     const size_t es = p.i64 ? 8 : 4;
+    // dwords per row: mp, or mp / 2 in the packed form (two columns per dword,
+    // halves offset by 2^15, row entries d_2j + 2^16 d_2j+1 modulo 2^32)
+    const int W = p.pack16 ? mp / 2 : mp;
+    const int64_t H = 1 << 15;
+    auto col = [&](int x, int y) -> int64_t { return y < m ? A.at(x, y) : 0; };
+    auto half = [](int64_t v) { return (uint32_t)((uint64_t)v & 0xffffu); };
     p.off_base = 0;
-    p.off_hid = align256(es * (size_t)mp);
-    p.off_mid = align256(p.off_hid + es * (size_t)std::max(nh, 1) * mp);
-    p.off_offs = align256(p.off_mid + es * (size_t)std::max(C, 1) * mp);
-    const int RS = (mp + 15) & ~15;   // subset-operand row stride (scalar loads of 8 dwords)
+    p.off_hid = align256(es * (size_t)W);
+    p.off_mid = align256(p.off_hid + es * (size_t)std::max(nh, 1) * W);
+    p.off_offs = align256(p.off_mid + es * (size_t)std::max(C, 1) * W);
+    const int RS = (W + 15) & ~15;   // subset-operand row stride (scalar loads of 8 dwords)
     p.off_tab = align256(p.off_offs + 4 * (size_t)NS * RS);
     const size_t end = align256(p.off_tab + 8 * std::max<size_t>(tab.size(), 1));
     p.blob.assign(end, 0);
-    for (int y = 0; y < mp; ++y) {
-        int64_t b = 0;
-        if (y < m) {
-            if (fixed0) b += A.at(0, y);
-            for (int c = 0; c < C; ++c) b += A.at(mid0 + c, y);
-        }
-        if (p.i64) put<int64_t>(p.blob, p.off_base, y, b);
-        else put<uint32_t>(p.blob, p.off_base, y, (uint32_t)(b + BIAS));
+    std::vector<int64_t> base(mp, 0);
+    for (int y = 0; y < m; ++y) {
+        if (fixed0) base[y] += A.at(0, y);
+        for (int c = 0; c < C; ++c) base[y] += A.at(mid0 + c, y);
+    }
+    for (int j = 0; j < W; ++j) {
+        if (p.pack16) put<uint32_t>(p.blob, p.off_base, j, half(base[2 * j] + H) | (half(base[2 * j + 1] + H) << 16));
+        else if (p.i64) put<int64_t>(p.blob, p.off_base, j, base[j]);
+        else put<uint32_t>(p.blob, p.off_base, j, (uint32_t)(base[j] + BIAS));
     }
     auto row = [&](size_t off, int slot, int x) {
-        for (int y = 0; y < mp; ++y) {
-            const int64_t v = y < m ? A.at(x, y) : 0;
-            if (p.i64) put<int64_t>(p.blob, off, (size_t)slot * mp + y, v);
-            else put<int32_t>(p.blob, off, (size_t)slot * mp + y, (int32_t)v);
+        for (int j = 0; j < W; ++j) {
+            const size_t at = (size_t)slot * W + j;
+            if (p.pack16) put<uint32_t>(p.blob, off, at, (uint32_t)(uint64_t)(col(x, 2 * j) + 65536 * col(x, 2 * j + 1)));
+            else if (p.i64) put<int64_t>(p.blob, off, at, col(x, j));
+            else put<int32_t>(p.blob, off, at, (int32_t)col(x, j));
         }
     };
     for (int h = 0; h < nh; ++h) row(p.off_hid, h, h0 + h);
     for (int c = 0; c < C; ++c) row(p.off_mid, c, mid0 + c);
-    for (int sub = 0; sub < NS; ++sub)
-        for (int y = 0; y < mp; ++y) {
-            int64_t low = 0;
-            if (y < m)
-                for (int i = 0; i < R; ++i)
-                    if ((sub >> i) & 1) low += A.at(low0 + i, y);
-            put<uint32_t>(p.blob, p.off_offs, (size_t)sub * RS + y, (uint32_t)(BIAS - low));
+    for (int sub = 0; sub < NS; ++sub) {
+        std::vector<int64_t> low(mp, 0);
+        for (int y = 0; y < m; ++y)
+            for (int i = 0; i < R; ++i)
+                if ((sub >> i) & 1) low[y] += A.at(low0 + i, y);
+        for (int j = 0; j < W; ++j) {
+            const uint32_t o = p.pack16 ? (half(H - low[2 * j]) | (half(H - low[2 * j + 1]) << 16))
+                                        : (uint32_t)(BIAS - low[j]);
+            put<uint32_t>(p.blob, p.off_offs, (size_t)sub * RS + j, o);
         }
+    }
     for (size_t i = 0; i < tab.size(); ++i) put<uint64_t>(p.blob, p.off_tab, i, tab[i]);
 }
 
@@ -497,11 +509,12 @@ bool use_wide(Plan& p, int states)
 // int32 binary kernel: the SGPR-operand kernel with sh.sgpr_r low rows when it
 // exists for this width, else the VGPR-operand kernel with as many low rows as
 // its register budget allows
-bool dary_sgpr_for(const SweepShape& sh, int d, int mp)
+// d-ary variant for a problem: 0 VGPR operands, 1 SGPR operands, 16 packed 16-bit
+int dary_variant(const SweepShape& sh, int d, int mp)
 {
     const int cls = variant_class(PK_LD, d);
     const int tuned = cls >= 0 ? sh.variant[cls][variant_bucket(mp)] : -1;
-    return (tuned >= 0 ? tuned : sh.dary_sgpr) != 0;
+    return tuned >= 0 ? tuned : sh.dary_sgpr;
 }
 
 int bin_variant(const Plan& p, const SweepShape& sh)
@@ -552,6 +565,43 @@ void pick_bin32(Plan& p, const SweepShape& sh, Mat const& A)
     }
     p.R = std::max(0, bin_rmax(p.mp, p.kind) - (sh.r_drop ? 1 : 0));
     p.kernel = kernel_bin32(p.kind, p.mp, p.R);
+}
+
+// d-ary register kernel of a plan (p.mp set, p.i64 known): the packed 16-bit
+// kernel where the variant asks for it and every column bound fits, else the
+// SGPR-operand kernel, else the VGPR-operand or int64 one, else the wide kernel.
+// `rows` is the number of rows the sweep can give low rows (range plans pad with
+// zero rows and pass a large value).  Sets p.kernel, p.R and p.pack16; false if no
+// kernel holds the problem.
+bool pick_dary(Plan& p, const SweepShape& sh, const Mat& A, int rows)
+{
+    const int d = p.d;
+    p.kernel = nullptr;
+    p.pack16 = 0;
+    p.bias = 0;
+    if (A.m <= MAX_MP && d <= MAX_D && !p.i64) {
+        const int v = dary_variant(sh, d, p.mp);
+        if (v == VARIANT_PACK16 && rows >= 1 + dary16_r(d) && pack16_fits(p, A)) {
+            p.kernel = kernel_dary16s(d, p.mp / 2);
+            if (p.kernel) {
+                p.pack16 = 1;
+                p.R = dary16_r(d);
+                return true;
+            }
+        }
+        if (v != 0 && rows >= 1 + DARY_RS) {
+            p.kernel = kernel_dary32s(d, p.mp);
+            if (p.kernel) {
+                p.R = DARY_RS;
+                return true;
+            }
+        }
+    }
+    if (A.m <= MAX_MP && d <= MAX_D) p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
+    if (!p.kernel && !use_wide(p, d)) return false;
+    // the register kernel scores R low rows per state; the others walk every row
+    p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    return true;
 }
 
 // Switch an int32 binary plan built for R = 5 to the int8-MFMA kernel when its
@@ -712,20 +762,9 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
 
     // d >= 3, d < n
     p.mp = pad_dary(A.m);
-    p.kernel = nullptr;
-    if (A.m <= MAX_MP && d <= MAX_D && !p.i64 && dary_sgpr_for(sh, d, p.mp) && A.n >= 1 + DARY_RS) {
-        p.kernel = kernel_dary32s(d, p.mp);
-        if (p.kernel) p.R = DARY_RS;
-    }
-    if (!p.kernel) {
-        if (A.m <= MAX_MP && d <= MAX_D)
-            p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
-        if (!p.kernel && !use_wide(p, d)) {
-            p.status = LD_ETOOBIG;
-            return p;
-        }
-        // the register kernel scores R low rows per state; the others walk every row
-        p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    if (!pick_dary(p, sh, A, A.n)) {
+        p.status = LD_ETOOBIG;
+        return p;
     }
     // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
     // row is fixed (message 0), which is the paper's fix-one-entry reduction
@@ -755,7 +794,10 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     if (sh.dary_lanes > 0) {
         auto lanes = [&](int pt, int pf) { return rgs_count(pt, d) * std::pow((double)d, pf); };
         auto trade = [&]() {
-            if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)(1 << 20))
+            // a longer restricted-growth prefix removes no more words once the table
+            // holds a few thousand strings (the relabelling factor is then d! already),
+            // but the host builds and uploads the table on every plan
+            if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)RGS_TRADE_MAX)
                 ++p.P_tab;
             else
                 ++P;
@@ -870,18 +912,9 @@ Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q
 
     // d >= 3: row 0 fixed at message 0; rows 1..n-q-1 mid; the last q rows prefix
     p.mp = pad_dary(m);
-    p.kernel = nullptr;
-    if (m <= MAX_MP && d <= MAX_D && !p.i64 && dary_sgpr_for(get_shape(), d, p.mp)) {
-        p.kernel = kernel_dary32s(d, p.mp);
-        if (p.kernel) p.R = DARY_RS;
-    }
-    if (!p.kernel) {
-        if (m <= MAX_MP && d <= MAX_D) p.kernel = p.i64 ? kernel_dary64(d, p.mp) : kernel_dary32(d, p.mp);
-        if (!p.kernel && !use_wide(p, d)) {
-            p.status = LD_ETOOBIG;
-            return p;
-        }
-        p.R = (!p.wide && !p.i64) ? dary_r(p.mp, d) : 0;
+    if (!pick_dary(p, get_shape(), A, 1 << 20)) {
+        p.status = LD_ETOOBIG;
+        return p;
     }
     // rows 1..n-q-1 give the C mid rows and the R low rows (zero rows pad them when
     // there are fewer than R: a zero row changes no message sum)

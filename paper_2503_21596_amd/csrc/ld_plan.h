@@ -27,15 +27,17 @@ struct SweepShape {
                              // rest of the rows become prefix rows (batch planning)
     int dary_lanes = 1 << 19;  // d >= 3: move mid rows into the prefix until this many
                                // lanes exist (0: keep dary_cwords words per lane)
-    int sgpr_r = 5;            // int32 binary kinds: low rows of the SGPR-operand kernel
+    int sgpr_r = 16;           // int32 binary kinds: low rows of the SGPR-operand kernel
                                // (4 or 5); 0 selects the VGPR-operand kernel; 8 the kernel
                                // whose state update runs on the matrix cores (int8 MFMA,
                                // R = 5) where the problem's operands fit it; 16 the packed
                                // 16-bit kernel (R = 5) where every column bound fits it
-    int dary_sgpr = 1;         // 1: d-ary int32 problems use the SGPR-operand kernel where built
+    int dary_sgpr = 16;        // d-ary int32 problems (d = 3, 4): 16 the packed 16-bit kernel where
+                               // every column bound fits it, 1 the SGPR-operand kernel where built,
+                               // 0 the VGPR-operand kernel
     // tuned kernel variant per (kind class, padded-width bucket); -1 = the setting
     // above.  Classes: 0 L1 / L_marg, 1 L2, 2 L_3, 3 L_4; buckets: mp in (16b, 16b + 16].
-    // Binary classes hold sgpr_r (0, 4, 5, 8, 16), d-ary classes dary_sgpr (0, 1).
+    // Binary classes hold sgpr_r (0, 4, 5, 8, 16), d-ary classes dary_sgpr (0, 1, 16).
     int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int merge = 1;             // 1: merge proportional rows / columns and (d >= 2) uniform-
                                // sign columns before planning (exact reductions)

@@ -34,6 +34,13 @@ constexpr bool dary_fits(int mp, int d) { return d * mp <= 192; }
 constexpr int DARY_RS = 3;
 constexpr bool dary_s_fits(int mp, int d) { return (d == 3 || d == 4) && d * mp <= 160; }
 
+// packed 16-bit d-ary kernels (two columns per dword, VARIANT_PACK16), d = 3, 4,
+// while the d message vectors take at most 96 VGPRs; by dword count (mp / 2).
+// Low rows per state: 4 for d = 3 (81 words), 3 for d = 4 (64 words; with 4 the
+// 256 assignments of the block maximum do not fit the registers beside the state)
+constexpr int dary16_r(int d) { return d == 3 ? 4 : 3; }
+constexpr bool dary16_fits(int words, int d) { return (d == 3 || d == 4) && d * words <= 96; }
+
 // d-ary low rows scored per state: the largest R <= 2 whose 2^R - 1 subset
 // operands fit beside the d state vectors, (d + 2^R - 1) * mp <= 200
 constexpr int dary_r(int mp, int d)
@@ -59,6 +66,7 @@ constexpr int VARIANT_MFMA = 8;   // binary variant value selecting kernel_mfma
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
 const void* kernel_dary32s(int d, int mp);   // SGPR-operand d-ary kernel (DARY_RS low rows)
+const void* kernel_dary16s(int d, int words);   // packed 16-bit d-ary kernel (dary16_r(d) low rows)
 const void* kernel_dary64(int d, int mp);
 const void* kernel_sumabs_many();
 const void* kernel_wide();

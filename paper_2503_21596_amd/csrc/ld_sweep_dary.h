@@ -166,12 +166,28 @@ struct Dary32 {
 // for every subset S; a mid step recomputes the 2^R norms of the two messages it
 // touches, and the best of the block's d^R words is the maximum over every
 // assignment of the low rows to messages of sum_k X[k][rows sent to k].
-template <int MP, int DD, int R>
+//
+// PK = true is the packed 16-bit form (as Bin16S): MP counts dwords of two columns
+// each (column 2j in bits 0..15), states and operands offset by 2^15 per half, row
+// entries stored as d_2j + 2^16 d_2j+1 modulo 2^32, and one v_sad_u16 scores both
+// columns of a dword.  It needs sum_x |M_xy| <= 2^15 - 1 for every column: then
+// every per-message column sum, with or without low rows added, lies in
+// (-2^15, 2^15), so no half ever carries into the other.
+template <int MP, int DD, int R, bool PK = false>
 struct Dary32S {
     static constexpr int NS = 1 << R;
     static constexpr int RS = (MP + 15) & ~15;
     static constexpr int N8 = (MP + 7) / 8;
+    static constexpr uint32_t ZERO = PK ? 0x80008000u : 0x80000000u;   // an empty message's state
     static_assert(NS % 4 == 0, "four subset streams per group");
+
+    __device__ static __forceinline__ uint32_t sad(uint32_t x, uint32_t o, uint32_t acc)
+    {
+        if constexpr (PK)
+            return sad_u16_s(x, o, acc);
+        else
+            return sad_u32_s(x, o, acc);
+    }
 
     // X[s] = sum_y |g_y - o_s,y| for the NS subset operands (o_0 = 2^31)
     __device__ static __forceinline__ void refresh(const uint32_t (&g)[MP], uint64_t ob, uint32_t (&X)[NS])
@@ -188,10 +204,10 @@ struct Dary32S {
                     constexpr int y0 = 8 * c;
                     if (y0 + j >= MP) continue;
                     const uint32_t x = g[y0 + j];
-                    a[0] = sad_u32_s(x, o0[j], a[0]);
-                    a[1] = sad_u32_s(x, o1[j], a[1]);
-                    a[2] = sad_u32_s(x, o2[j], a[2]);
-                    a[3] = sad_u32_s(x, o3[j], a[3]);
+                    a[0] = sad(x, o0[j], a[0]);
+                    a[1] = sad(x, o1[j], a[1]);
+                    a[2] = sad(x, o2[j], a[2]);
+                    a[3] = sad(x, o3[j], a[3]);
                 }
             });
             X[s0] = a[0];
@@ -239,7 +255,7 @@ struct Dary32S {
 #pragma unroll
         for (int k = 1; k < DD; ++k)
 #pragma unroll
-            for (int y = 0; y < MP; ++y) g[k][y] = 0x80000000u;
+            for (int y = 0; y < MP; ++y) g[k][y] = ZERO;
 
         uint64_t code = 0, fr = v;
         if (D.P_tab > 0) {

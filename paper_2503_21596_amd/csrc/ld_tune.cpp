@@ -108,10 +108,10 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
     std::fprintf(f,
                  "  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
-                 "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"plain_p_min\": %d,\n"
-                 "  \"plain_dary_lanes\": %d,\n  \"measured\": [%s]\n}\n",
+                 "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"dary_variant\": %d,\n"
+                 "  \"plain_p_min\": %d,\n  \"plain_dary_lanes\": %d,\n  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
-                 t.plain_r_drop, t.sgpr_r, t.plain_p_min, t.plain_dary_lanes, notes.c_str());
+                 t.plain_r_drop, t.sgpr_r, t.dary_variant, t.plain_p_min, t.plain_dary_lanes, notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -146,6 +146,7 @@ void set_tuning(const Tuning& t)
     s.c_goal = t.plain_c_goal;
     s.r_drop = t.plain_r_drop;
     s.sgpr_r = t.sgpr_r;
+    s.dary_sgpr = t.dary_variant;
     s.dary_lanes = t.plain_dary_lanes;
     std::memcpy(s.variant, t.variant, sizeof s.variant);
     set_shape(s);
@@ -281,14 +282,14 @@ int ld_autotune(const char* path, double budget_seconds)
 
     // kernel variant per kind class and width bucket (binary: packed 16-bit kernel,
     // SGPR-operand kernel with 5 or 4 low rows, VGPR-operand kernel, int8-MFMA
-    // kernel; d-ary: SGPR- or
-    // VGPR-operand kernel), timed on one problem each of
-    // a few milliseconds (L1 with 33 rows, L2 with 32, L_3 with 19, L_4 with 15;
+    // kernel; d-ary: packed 16-bit, SGPR- or VGPR-operand kernel), timed on one
+    // problem each of
+    // a few milliseconds (L1 with 33 rows, L2 with 32, L_3 with 22, L_4 with 19;
     // width 16b + 14, or square for the narrowest L1 bucket so that the planner
     // does not transpose it)
     {
         Rng r{0x7a2};
-        const int rows[4] = {33, 32, 19, 15};
+        const int rows[4] = {33, 32, 22, 19};
         const int dval[4] = {1, 2, 3, 4};
         for (int c = 0; c < 4 && now_s() < t_end; ++c)
             for (int b = 0; b < 4 && now_s() < t_end; ++b) {
@@ -297,7 +298,8 @@ int ld_autotune(const char* path, double budget_seconds)
                 std::vector<int32_t> M((size_t)n * m);
                 for (auto& x : M) x = r.uniform(-100, 100);
                 std::vector<int> options =
-                    c < 2 ? std::vector<int>{VARIANT_PACK16, 5, 4, 0, VARIANT_MFMA} : std::vector<int>{1, 0};
+                    c < 2 ? std::vector<int>{VARIANT_PACK16, 5, 4, 0, VARIANT_MFMA}
+                          : std::vector<int>{VARIANT_PACK16, 1, 0};
                 double bt = 1e30;
                 int pick = -1;
                 for (int o : options) {
@@ -356,6 +358,8 @@ int ld_load_tuning(const char* path)
     if (read_key(text, "plain_r_drop", &v)) t.plain_r_drop = v != 0;
     if (read_key(text, "sgpr_r", &v))
         t.sgpr_r = (v == 4 || v == 5 || v == VARIANT_MFMA || v == VARIANT_PACK16) ? (int)v : 0;
+    if (read_key(text, "dary_variant", &v))
+        t.dary_variant = v == VARIANT_PACK16 ? VARIANT_PACK16 : v != 0 ? 1 : 0;
     if (read_key(text, "plain_dary_lanes", &v)) t.plain_dary_lanes = (int)std::max(0.0, std::min(v, 1073741824.0));
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < 4; ++b) {

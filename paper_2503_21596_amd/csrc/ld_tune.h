@@ -14,7 +14,9 @@ struct Tuning {
     int plain_p_min = 19;         // plain calls: at least 2^this lanes when the problem has them
     int plain_c_goal = 12;        // plain calls: aim for 2^this words per prefix
     int plain_r_drop = 0;         // plain calls: one low row fewer than the register budget allows
-    int sgpr_r = 5;               // int32 binary kinds: low rows of the SGPR-operand kernel (0: VGPR kernel)
+    int sgpr_r = 16;              // int32 binary kinds: 16 the packed 16-bit kernel where it fits, else
+                                  // low rows of the SGPR-operand kernel (4, 5; 0: VGPR kernel)
+    int dary_variant = 16;        // int32 d = 3, 4: 16 packed where it fits, 1 SGPR operands, 0 VGPR
     int plain_dary_lanes = 1 << 19;  // plain calls, d >= 3: trade mid rows for prefix rows until
                                      // this many lanes exist
     // kernel variant per (kind class, width bucket), as SweepShape::variant (-1: the above)

@@ -251,12 +251,12 @@ def test_plan_dary_lane_trading():
 
 
 def test_plan_kernel_family_and_mfma_selection():
-    """ld_plan_info.kernel names the sweep kernel: the headline takes the SGPR-operand
-    kernel (1); with variant 8 the int8-MFMA kernel (2) where the mid-row deltas fit
-    int8 and 1 <= C <= 16, else the SGPR-operand kernel with 5 low rows."""
+    """ld_plan_info.kernel names the sweep kernel: the headline takes the packed 16-bit
+    kernel (5); with variant 8 the int8-MFMA kernel (2) where the mid-row deltas fit
+    int8 and 1 <= C <= 16, else the SGPR-operand kernel with 5 low rows (1)."""
     M = synth.config_42_l1(0)
     p = L.plan(M, 1, 0)
-    assert p["kernel"] == 1 and p["R"] == 5
+    assert p["kernel"] == 5 and p["R"] == 5
     try:
         L.set_sweep_shape(0, 0, -1, 0, 8, -1)
         p = L.plan(M, 1, 0)
@@ -265,11 +265,11 @@ def test_plan_kernel_family_and_mfma_selection():
         p = L.plan(big, 1, 0)
         assert p["kernel"] == 1 and p["R"] == 5
         assert L.plan(synth.matrix(5, 26, 26, -120, 120, "abi"), 2, 0)["kernel"] == 2
-        assert L.plan(synth.matrix(6, 12, 20, -9, 9, "abi"), 3, 0)["kernel"] in (0, 1)   # d >= 3: d-ary
+        assert L.plan(synth.matrix(6, 12, 20, -9, 9, "abi"), 3, 0)["kernel"] in (0, 1, 5)   # d >= 3: d-ary
         assert L.plan(synth.matrix(7, 3, 70, 1, 9, "abi"), 1, 0)["kernel"] == 4          # > 64 columns: wide
     finally:
         L.load_tuning(L.TUNING_PATH)
-    assert L.plan(M, 1, 0)["kernel"] == 1
+    assert L.plan(M, 1, 0)["kernel"] == 5
 
 
 def test_batch_plan_dary_step_count_fits_32_bits(tmp_path):

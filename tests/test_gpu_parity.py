@@ -179,23 +179,63 @@ def test_reductions_planted(d, marg):
         check(M, d, marg)
 
 
-@pytest.mark.parametrize("dary_sgpr", [0, 1])
+@pytest.mark.parametrize("dary_sgpr", [0, 1, 16])
 def test_dary_kernel_variants(dary_sgpr):
-    """Both int32 d-ary kernels (subset operands in VGPRs with up to two low rows,
-    or streamed through SGPRs with three) against the oracle, d = 3, 4, every
-    column count up to the SGPR kernel's limit and row counts around R + 1."""
+    """The int32 d-ary kernels (subset operands in VGPRs with up to two low rows,
+    streamed through SGPRs with three, or two columns per register as 16-bit
+    halves with four) against the oracle, d = 3, 4, every column count up to the
+    SGPR kernels' limits, row counts around R + 1 and plans with several mid rows."""
     say("dary variants", dary_sgpr)
     try:
         L.set_sweep_shape(0, 0, -1, 0, -1, dary_sgpr)
         for i, (n, m, d) in enumerate([(4, 5, 3), (5, 8, 3), (7, 13, 3), (9, 32, 3), (10, 52, 3), (8, 3, 3),
-                                       (5, 6, 4), (7, 17, 4), (8, 40, 4), (9, 24, 4), (6, 1, 4)]):
+                                       (5, 6, 4), (7, 17, 4), (8, 40, 4), (9, 24, 4), (6, 1, 4),
+                                       (12, 20, 3), (13, 47, 3), (12, 64, 3), (11, 9, 4), (10, 48, 4),
+                                       (11, 52, 4), (6, 2, 3)]):
             M = synth.matrix(950 + i, n, m, -500, 500, "dvariants")
             p = L.plan(M, d, 0)
-            if dary_sgpr and p["kind_name"] == "L_d" and p["i64"] == 0 and p["mp"] * d <= 160:
-                assert p["R"] == 3, p
+            if p["kind_name"] == "L_d" and p["i64"] == 0:
+                if dary_sgpr == 1 and p["mp"] * d <= 160:
+                    assert p["R"] == 3 and p["kernel"] == 1, p
+                if dary_sgpr == 16 and n >= 5 and p["mp"] // 2 * d <= 96:
+                    assert p["R"] == (4 if d == 3 else 3) and p["kernel"] == 5, p
             check(M, d, 0)
+        # plans that walk mid rows with the Gray code (and batch plans with more),
+        # against the oracle's split-table form
+        for i, (n, m, d) in enumerate([(14, 20, 3), (15, 24, 3), (13, 20, 4), (14, 16, 4)]):
+            M = synth.matrix(1950 + i, n, m, -500, 500, "dvariants2")
+            assert L.plan(M, d, 0)["C"] >= 1
+            want = oracle.ld_split(M, d)
+            check(M, d, 0, want)
+            assert L.ld_norm_batch([(M, d, 0)])[0] == want
     finally:
         L.set_sweep_shape(0, 0, -1, 0, -1, 1)
+
+
+def test_dary_packed_bounds():
+    """The packed 16-bit d-ary kernel at the edge of its range: a column with
+    sum |M_xy| = 2^15 - 1 is taken, 2^15 falls back to the SGPR-operand kernel;
+    all rows of the extreme column sent to one message reach a sum of 2^15 - 1."""
+    say("dary packed bounds")
+    try:
+        L.set_sweep_shape(0, 0, -1, 0, -1, 16)
+        for n, m, d in [(9, 10, 3), (11, 21, 4), (13, 30, 3)]:
+            key = synth.stream_key(n + 100 * d, "dedge")
+            sg = np.where(synth.uniform_ints(key, n * m, 0, 1) == 0, -1, 1).reshape(n, m)
+            mag = synth.uniform_ints(synth.stream_key(n, "dmag"), n * m, 1, 50).reshape(n, m)
+            for target, packed in [(32767, True), (32768, False)]:
+                A = (sg * mag).astype(np.int64)
+                col = np.abs(A[:, 3])
+                A[:, 3] = sg[:, 3] * (col * (target // col.sum()))
+                A[0, 3] += sg[0, 3] * (target - np.abs(A[:, 3]).sum())
+                assert np.abs(A[:, 3]).sum() == target
+                A = A.astype(np.int32)
+                p = L.plan(A, d, 0)
+                assert p["kernel"] == (5 if packed else 1), (target, d, p)
+                check(A, d, 0)
+    finally:
+        L.set_sweep_shape(0, 0, -1, 0, -1, 1)
+        L.load_tuning(L.TUNING_PATH)
 
 
 @pytest.mark.parametrize("sgpr_r", [0, 4, 5, 16])

@@ -170,19 +170,20 @@ def test_mfma_results_wait(obj, tmp_path):
 
 
 DEPTH = re.compile(r"^\s*;.*Depth=(\d+)")
-DARY_S = re.compile(r"^(_ZN2ld9k_dary32sILi(\d+)ELi(\d+)EEEvNS_5QArgsE):")
+DARY_S = re.compile(r"^(_ZN2ld9k_dary(32|16)sILi(\d+)ELi(\d+)EEEvNS_5QArgsE):")
 
 
 def gray_loop_spills(asm_lines):
-    """Per k_dary32s instantiation of a compiler assembly listing: scratch
-    instructions at the deepest loop level that holds v_sad_u32 (the Gray loop)."""
+    """Per k_dary32s / k_dary16s instantiation of a compiler assembly listing,
+    keyed (bits, width, d): scratch instructions at the deepest loop level that
+    holds v_sad_u32 or v_sad_u16 (the Gray loop)."""
     out = {}
     cur = None
     depth = 0
     for line in asm_lines:
         m = DARY_S.match(line)
         if m:
-            cur = (int(m.group(2)), int(m.group(3)))
+            cur = (int(m.group(2)), int(m.group(3)), int(m.group(4)))
             out[cur] = {"sad": {}, "scratch": {}}
             depth = 0
             continue
@@ -198,7 +199,7 @@ def gray_loop_spills(asm_lines):
         if d:
             depth = int(d.group(1))
             continue
-        if "v_sad_u32" in line:
+        if "v_sad_u32" in line or "v_sad_u16" in line:
             out[cur]["sad"][depth] = out[cur]["sad"].get(depth, 0) + 1
         if "scratch_" in line:
             out[cur]["scratch"][depth] = out[cur]["scratch"].get(depth, 0) + 1
@@ -219,7 +220,10 @@ def test_dary_gray_loop_has_no_spills(tmp_path):
     listing = [f for f in os.listdir(tmp_path) if f.endswith(".s") and "gfx950" in f]
     assert len(listing) == 1, os.listdir(tmp_path)
     spills = gray_loop_spills(open(tmp_path / listing[0]).read().splitlines())
-    assert len(spills) == 23, sorted(spills)   # d = 3: 4 .. 52 columns, d = 4: 4 .. 40
+    # 32-bit: d = 3 at 4 .. 52 columns, d = 4 at 4 .. 40; packed: d = 3 at 2 .. 32
+    # dwords, d = 4 at 2 .. 24
+    assert len([k for k in spills if k[0] == 32]) == 23, sorted(spills)
+    assert len([k for k in spills if k[0] == 16]) == 28, sorted(spills)
     assert all(v == 0 for v in spills.values()), {k: v for k, v in spills.items() if v}
 
 
