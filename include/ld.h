@@ -45,6 +45,8 @@ extern "C" {
 #define LD_PENDING 6     /* server: result not ready yet                                  */
 #define LD_ENOTFOUND 7   /* server: unknown ticket                                        */
 #define LD_ECANCELED 8   /* server: request cancelled before it completed                 */
+#define LD_ESCRATCH 9    /* ld_norm_noalloc: the problem's device image exceeds the static
+                            scratch array (LD_NOALLOC_SCRATCH_BYTES)                      */
 
 /* ld_norm -- L1 / L_marg / L_d of one matrix (definitions above).
  * Preprocessing keeps the value exactly: all-zero rows and columns are dropped
@@ -54,6 +56,26 @@ extern "C" {
  * Synchronous: returns after the result is on the host.
  * Returns the value, or INT64_MIN with ld_last_error() set. */
 int64_t ld_norm(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals);
+
+/* ld_norm_noalloc -- ld_norm for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same planning, kernels and value as ld_norm.  The problem's device
+ * image (tables, descriptor, queue head, result slot) is placed in a static
+ * device array of LD_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds
+ * from load until the process ends; the call makes no hipMalloc, hipFree or
+ * hipHostMalloc.  A problem whose image exceeds the array (far beyond the
+ * register-kernel shapes: the wide kernel's int64 tables of about a million
+ * entries) fails with LD_ESCRATCH before anything is launched.
+ * M: host, row-major n x m, read during the call.  value: host pointer receiving
+ * the result (INT64_MIN on error).  hip_stream: a hipStream_t, or NULL for the
+ * null stream; the call returns after the result is on the host.  Every call on a
+ * GPU uses that GPU's one array and overwrites it (the queue head and result slot
+ * are reset by a kernel each call); calls in one process take turns on a lock per
+ * device, so they do not overlap.  Returns LD_OK or an error code, also in
+ * ld_last_error(). */
+#define LD_NOALLOC_SCRATCH_BYTES (1u << 20)
+int ld_norm_noalloc(const int32_t* M, int32_t n, int32_t m, int32_t d, int32_t marginals, int64_t* value,
+                    void* hip_stream);
 
 /* One problem of a batch. */
 typedef struct {

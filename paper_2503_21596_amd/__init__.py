@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libld.so")
 TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json")
 INT64_MIN = -(1 << 63)
 
-LD_OK, LD_EINVAL, LD_EMARG_D, LD_ETOOBIG, LD_EHIP, LD_EBUSY, LD_PENDING, LD_ENOTFOUND, LD_ECANCELED = range(9)
+LD_OK, LD_EINVAL, LD_EMARG_D, LD_ETOOBIG, LD_EHIP, LD_EBUSY, LD_PENDING, LD_ENOTFOUND, LD_ECANCELED, \
+    LD_ESCRATCH = range(10)
 
 PLAN_KINDS = {0: "L1", 1: "L_marg", 2: "L2", 3: "L_d", 4: "sum|M|", 5: "zero"}
 
@@ -69,6 +70,7 @@ SIGNATURES = {
     "ld_norm": (_I64, [_P, _I32, _I32, _I32, _I32]),
     "ld_norm_batch": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
     "ld_norm_range": (_I64, [_P, _I32, _I32, _I32, _I32, _I32, _U64, _U64]),
+    "ld_norm_noalloc": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P]),
     "ld_argmax": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _P]),
     "ld_norm_resumable": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, ctypes.c_char_p, ctypes.c_double,
                                          ctypes.c_double, _P]),
@@ -163,6 +165,17 @@ def ld_norm_range(M, d: int, marginals: int, q: int, prefix_begin: int, prefix_e
     if v == INT64_MIN:
         raise _err()
     return int(v)
+
+
+def ld_norm_noalloc(M, d: int = 1, marginals: int = 0, stream=None) -> int:
+    """ld_norm on the library's static device scratch array (no device allocation)."""
+    a = _mat(M)
+    v = ctypes.c_int64(0)
+    s = stream.cuda_stream if stream is not None else None
+    rc = lib().ld_norm_noalloc(a.ctypes.data, a.shape[0], a.shape[1], int(d), int(marginals), ctypes.byref(v), s)
+    if rc != LD_OK:
+        raise _err(rc)
+    return int(v.value)
 
 
 def ld_argmax(M, d: int = 1, marginals: int = 0):

@@ -37,6 +37,7 @@ UNITS = [
     ("ld_tune.cpp", [], "tune.o"),
     ("ld_argmax.cpp", [], "argmax.o"),
     ("ld_resume.cpp", [], "resume.o"),
+    ("ld_noalloc.cpp", [], "noalloc.o"),
 ]
 
 

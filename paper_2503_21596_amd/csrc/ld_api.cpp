@@ -282,6 +282,7 @@ const char* ld_error_string(int code)
     case LD_PENDING: return "result pending";
     case LD_ENOTFOUND: return "unknown ticket";
     case LD_ECANCELED: return "request cancelled";
+    case LD_ESCRATCH: return "problem image exceeds the static scratch array of ld_norm_noalloc";
     default: return "unknown error code";
     }
 }

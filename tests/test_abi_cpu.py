@@ -313,3 +313,20 @@ def test_small_problems_take_lanes_before_mid_rows():
     assert p["C"] == 4 and p["P"] == 17, p
     p = L.plan(synth.config_42_l1(0), 1, 0)
     assert p["C"] == 16 and p["P"] == 20, p
+
+
+def test_noalloc_refuses_images_beyond_its_array():
+    """ld_norm_noalloc checks the problem's device image against its static array
+    before any device call: a plan whose int64 tables exceed it gets LD_ESCRATCH
+    (no GPU needed), invalid arguments their usual codes."""
+    import ctypes
+    big = synth.matrix(8111, 20, 8000, -3, 3, "noalloc_big")
+    assert L.plan(big, 1, 0)["status"] == L.LD_OK
+    v = ctypes.c_int64(7)
+    rc = L.lib().ld_norm_noalloc(big.ctypes.data, 20, 8000, 1, 0, ctypes.byref(v), None)
+    assert rc == L.LD_ESCRATCH and v.value == np.iinfo(np.int64).min
+    assert L.lib().ld_last_error() == L.LD_ESCRATCH
+    M = synth.matrix(8110, 4, 4, -5, 5, "noalloc")
+    assert L.lib().ld_norm_noalloc(M.ctypes.data, 4, 4, 2, 1, ctypes.byref(v), None) == L.LD_EMARG_D
+    assert L.lib().ld_norm_noalloc(None, 4, 4, 1, 0, ctypes.byref(v), None) == L.LD_EINVAL
+    assert L.lib().ld_norm_noalloc(M.ctypes.data, 4, 4, 1, 0, None, None) == L.LD_EINVAL
