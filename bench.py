@@ -130,10 +130,17 @@ def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0)
     vals = [S.wait(t) for t in tickets]
     t_end = time.perf_counter()
     st = S.stats()
+    tm = S.timings()
     S.close()
     served = {"requests": count, "rate_per_s": rate, "solves_per_s": count / (t_end - t_start),
               "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-              "mean_wait_ms": st["mean_wait_ms"], "launches": st["launches"]}
+              "mean_wait_ms": st["mean_wait_ms"], "mean_plan_ms": st["mean_plan_ms"],
+              "mean_run_ms": st["mean_run_ms"], "launches": st["launches"],
+              # medians of the latency split (plan: submitting thread; wait: until the first
+              # step with the request's items is issued; run: from there to completion)
+              "p50_split_ms": {k: float(np.median([t[k] for t in tm])) for k in ("plan_ms", "wait_ms", "run_ms")}
+              if tm else None,
+              "express_share": float(np.mean([t["lane"] for t in tm])) if tm else None}
     # the same trace in real time through sequential plain calls: one thread waits
     # for each arrival (when idle) and serves the requests first come, first served
     durs = []
@@ -452,7 +459,8 @@ def main():
                      "ops_per_step": ops, "note": note,
                      "scoring_ops_per_step": sops,
                      "frac_scoring_only": words * sops / (kavg / 1e3) / INT32_VALU_PEAK,
-                     "valu_insts_per_step": (float(prof["valu_insts_per_launch"]) / words
+                     # lane-level: each wave64 instruction serves 64 lanes, one word each
+                     "valu_insts_per_step": (64.0 * float(prof["valu_insts_per_launch"]) / words
                                              if prof.get("valu_insts_per_launch") else None),
                      "valu_issue_frac": valu_issue,
                      "sclk_kernel_hz": sclk, "sclk_probe_hz": probe["sclk_hz"],

@@ -199,6 +199,13 @@ typedef struct {
     int32_t device;                 /* HIP device index                                     */
     double express_ms;              /* requests below this estimated device time take the
                                        express lane (0: 1 ms; negative: no express lane)    */
+    double idle_spin_ms;            /* an idle scheduler polls for arrivals this long before
+                                       it sleeps, keeping one host thread busy (0: 50 ms;
+                                       negative: it sleeps at once)                          */
+    int32_t min_items;              /* a request with that many 64-lane pieces is cut into at
+                                       least this many queue items, so that a small request
+                                       spreads over the device (0: 4096; negative: no floor,
+                                       items of words_per_item only)                          */
 } ld_server_config;
 
 typedef struct {
@@ -206,6 +213,8 @@ typedef struct {
     int32_t inflight, queued;
     double p50_ms, p99_ms, mean_ms;  /* latency: submit -> completion seen by the scheduler */
     double mean_wait_ms;             /* mean of submit -> first step issued                  */
+    double mean_plan_ms;             /* mean of submit -> queued (planning, submitting thread) */
+    double mean_run_ms;              /* mean of first step issued -> completion               */
 } ld_stats;
 
 typedef struct ld_server ld_server;
@@ -222,6 +231,20 @@ int ld_server_wait(ld_server* s, uint64_t ticket, int64_t* value);
 /* Cancel a queued or in-flight request (its remaining items are dropped). */
 int ld_server_cancel(ld_server* s, uint64_t ticket);
 void ld_server_stats(ld_server* s, ld_stats* out);
+/* Per-request latency split of completed requests (status LD_OK), oldest first:
+ * where a request's time went between submission and completion. */
+typedef struct {
+    uint64_t ticket;
+    int32_t lane;      /* 0 bulk, 1 express                                           */
+    int32_t items;     /* queue items the request was cut into                        */
+    double words;      /* assignments its sweep scores                                 */
+    double plan_ms;    /* submit -> queued: planning on the submitting thread          */
+    double wait_ms;    /* queued -> first step with its items issued                   */
+    double run_ms;     /* that step issued -> completion seen by the scheduler         */
+} ld_request_timing;
+/* Copies the timings of the first `max` completed requests (at most the last 2^20 are
+ * kept) to out; returns how many it wrote, or -1 for a null server. */
+int32_t ld_server_timings(ld_server* s, ld_request_timing* out, int32_t max);
 /* Drains in-flight steps, stops the scheduler, frees the device memory. */
 void ld_server_destroy(ld_server* s);
 

@@ -46,7 +46,14 @@ class ld_server_config(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_inflight_problems", ctypes.c_int32),
                 ("max_items_per_launch", ctypes.c_int32), ("words_per_item", ctypes.c_double),
                 ("step_ms", ctypes.c_double), ("max_queued", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("express_ms", ctypes.c_double)]
+                ("express_ms", ctypes.c_double), ("idle_spin_ms", ctypes.c_double),
+                ("min_items", ctypes.c_int32)]
+
+
+class ld_request_timing(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("lane", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("words", ctypes.c_double), ("plan_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double)]
 
 
 class ld_valu_probe_result(ctypes.Structure):
@@ -60,7 +67,8 @@ class ld_stats(ctypes.Structure):
                 ("rejected", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("items", ctypes.c_uint64), ("inflight", ctypes.c_int32),
                 ("queued", ctypes.c_int32), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
-                ("mean_ms", ctypes.c_double), ("mean_wait_ms", ctypes.c_double)]
+                ("mean_ms", ctypes.c_double), ("mean_wait_ms", ctypes.c_double),
+                ("mean_plan_ms", ctypes.c_double), ("mean_run_ms", ctypes.c_double)]
 
 
 # exported symbols and their signatures: name -> (restype, argtypes)
@@ -98,6 +106,7 @@ SIGNATURES = {
     "ld_server_wait": (ctypes.c_int, [_P, _U64, _P]),
     "ld_server_cancel": (ctypes.c_int, [_P, _U64]),
     "ld_server_stats": (None, [_P, _P]),
+    "ld_server_timings": (_I32, [_P, _P, _I32]),
     "ld_server_destroy": (None, [_P]),
     "ld_autotune": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_double]),
     "ld_load_tuning": (ctypes.c_int, [ctypes.c_char_p]),
@@ -368,9 +377,10 @@ class Server:
 
     def __init__(self, arena_bytes: int = 256 << 20, max_inflight_problems: int = 1024,
                  max_items_per_launch: int = 65536, words_per_item: float = 0.0, step_ms: float = 0.0,
-                 max_queued: int = 0, device: int = 0, express_ms: float = 0.0):
+                 max_queued: int = 0, device: int = 0, express_ms: float = 0.0, idle_spin_ms: float = 0.0,
+                 min_items: int = 0):
         cfg = ld_server_config(arena_bytes, max_inflight_problems, max_items_per_launch, words_per_item,
-                               step_ms, max_queued, device, express_ms)
+                               step_ms, max_queued, device, express_ms, idle_spin_ms, min_items)
         self._h = lib().ld_server_create(ctypes.byref(cfg))
         if not self._h:
             raise _err()
@@ -413,6 +423,15 @@ class Server:
         s = ld_stats()
         lib().ld_server_stats(self._h, ctypes.byref(s))
         return {f[0]: getattr(s, f[0]) for f in ld_stats._fields_}
+
+    def timings(self, max_records: int = 1 << 20) -> list:
+        """Per completed request: ticket, lane, items, words, plan_ms, wait_ms, run_ms."""
+        cap = max(1, min(int(max_records), int(self.stats()["completed"])))
+        buf = (ld_request_timing * cap)()
+        n = lib().ld_server_timings(self._h, buf, cap)
+        if n < 0:
+            raise _err(LD_EINVAL)
+        return [{f[0]: getattr(buf[i], f[0]) for f in ld_request_timing._fields_} for i in range(n)]
 
     def close(self):
         if self._h:

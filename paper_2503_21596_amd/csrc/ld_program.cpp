@@ -31,11 +31,26 @@ struct Rel {
 // does not matter, only that it grows with the columns and the messages).
 double word_cost(const Plan& p)
 {
+    // lane-level VALU instructions per word of the kernel the plan runs (measured
+    // counts: 22.4 for the packed 42-column L1 sweep, 44.1 for the 32-bit one, 9.95
+    // for the packed d = 3 sweep at 40 columns; the int64 and LDS kernels take about
+    // three instructions per 32-bit one)
+    const double W = p.pack16 ? p.mp / 2.0 : (double)p.mp;   // dwords per row
+    const double R = (double)p.R;
     switch (p.kind) {
     case PK_L1:
-    case PK_MARG: return p.m + 1.0;
-    case PK_L2: return 2.0 * p.m + 1.0;
-    case PK_LD: return 4.0 * p.m + p.d;
+    case PK_MARG:
+    case PK_L2: {
+        const double sides = p.kind == PK_L2 ? 2.0 : 1.0;
+        if (p.i64 || p.wide) return 3.0 * (sides * p.m + 1.0);
+        const double c = sides * W + W / std::ldexp(1.0, p.R) + 0.75;
+        return p.mfma ? 1.12 * c : c;
+    }
+    case PK_LD: {
+        if (p.i64 || p.wide) return 3.0 * (4.0 * p.m + p.d);
+        const double blk = std::pow((double)p.d, R);            // words per state
+        return (2.0 * std::ldexp(1.0, p.R) * W + blk * (p.d + 1.0)) / blk;
+    }
     default: return 1.0;
     }
 }
@@ -57,6 +72,13 @@ void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<
             const double want = std::floor(sh.item_words / wpp / sh.lanes_per_item);
             per = (uint64_t)sh.lanes_per_item * (uint64_t)std::max(1.0, want);
         }
+    }
+    if (sh.min_items > 0) {
+        // at least min_items items when the problem has that many wave-sized pieces,
+        // so that a small problem spreads over the device instead of a few waves
+        const uint64_t unit = wide ? 1 : p.mfma ? 2 : sh.lanes_per_item;
+        const uint64_t kmax = std::max<uint64_t>(1, p.n_prefix / (unit * sh.min_items));
+        per = std::min<uint64_t>(per, unit * kmax);
     }
     per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
     per = std::min<uint64_t>(per, 0xffffffffull);

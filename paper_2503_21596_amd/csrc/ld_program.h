@@ -50,7 +50,8 @@ struct ItemShape {
     uint32_t lanes_per_item = 64;   // prefixes per item for the register kernels
     double item_words = 0;          // if > 0: grow items up to about this many words
     uint32_t max_items = 1u << 20;  // per problem
-    uint32_t min_items = 0;         // single problems: keep at least this many items
+    uint32_t min_items = 0;         // keep at least this many items per problem when it has that
+                                    // many wave-sized pieces (single problems, server requests)
     // a launch shared by several problems: grow the items until the launch holds at
     // most about this many (pops on the one queue head serialize, tens of ns each)
     uint32_t max_launch_items = 1u << 16;

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -56,16 +57,28 @@ double now_s()
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Sustained VALU rate used to size steps (lane-ops/s); only step lengths depend
-// on it.  Item costs (split_items) count the ops of one lane of the wave that runs
-// the item, so an item occupies the device for about cost x 64 lane-ops.
-constexpr double STEP_OPS_PER_S = 3.0e13;
+// Sustained VALU rate used to size steps (lane-instructions/s: about 95 % of 256
+// CUs x 64 lanes x 2.37 GHz); only step lengths and the express threshold depend on
+// it.  Item costs (split_items) count the instructions of one lane of the wave that
+// runs the item, so an item occupies the device for about cost x 64 lane-instructions.
+constexpr double STEP_OPS_PER_S = 3.6e13;
 constexpr double COST_UNITS_PER_S = STEP_OPS_PER_S / 64.0;
+
+// An idle scheduler polls for new requests this long before it sleeps: longer than
+// the gaps of a few hundred requests per second, so that such a stream never waits
+// for a thread wake-up.  It keeps one host thread busy meanwhile.
+constexpr double IDLE_SPIN_S = 0.05;
+
+constexpr size_t TIMINGS_KEPT = (size_t)1 << 20;   // per-request timing records kept
+
+// least queue items of a request that has that many 64-lane pieces: about one per
+// resident wave of a sweep kernel (4 to 6 per SIMD on 1024 SIMDs)
+constexpr uint32_t SERVE_MIN_ITEMS = 4096;
 
 struct Request {
     uint64_t ticket = 0;
     Plan plan;
-    double t_submit = 0, t_done = 0, t_issue = 0;
+    double t_submit = 0, t_done = 0, t_issue = 0, t_queued = 0;
     int status = LD_PENDING;
     int64_t value = 0;
     // scheduling state
@@ -146,6 +159,7 @@ struct ld_server {
     // one step, not two (the gap between steps costs less: on the served traces
     // mean latency fell by about a seventh, p99 unchanged)
     int bulk_depth = 1;
+    double idle_spin_s = IDLE_SPIN_S;   // how long an idle scheduler polls for arrivals (config)
     uint8_t* arena_dev = nullptr;
     Desc* d_descs = nullptr;
     int64_t* d_results = nullptr;
@@ -160,6 +174,10 @@ struct ld_server {
 
     std::mutex mu;
     std::condition_variable cv;       // scheduler wake-up
+    // submissions so far and the stop request, readable without mu: an idle
+    // scheduler watches them for a while before it sleeps on cv
+    std::atomic<uint64_t> arrivals{0};
+    std::atomic<bool> stopping{false};
     std::condition_variable done_cv;  // request completion
     std::unordered_map<uint64_t, Request*> all;
     uint64_t next_ticket = 1;
@@ -169,8 +187,9 @@ struct ld_server {
 
     uint64_t st_submitted = 0, st_completed = 0, st_rejected = 0, st_launches = 0, st_items = 0;
     std::vector<double> latencies_ms;
-    double wait_sum_ms = 0;
-    uint64_t wait_n = 0;
+    std::deque<ld_request_timing> timings;   // completed requests, oldest first (bounded)
+    double wait_sum_ms = 0, plan_sum_ms = 0, run_sum_ms = 0;
+    uint64_t wait_n = 0, plan_n = 0, run_n = 0;
 
     ~ld_server()
     {
@@ -203,6 +222,21 @@ void finish(ld_server* S, Request* r, int status, int64_t value)
     if (status == LD_OK) {
         S->st_completed++;
         S->latencies_ms.push_back(1e3 * (r->t_done - r->t_submit));
+        if (r->t_issue > 0) {
+            S->run_sum_ms += 1e3 * (r->t_done - r->t_issue);
+            S->run_n++;
+        }
+        ld_request_timing t{};
+        t.ticket = r->ticket;
+        t.lane = r->lane;
+        t.items = (int32_t)r->items.size();
+        t.words = r->plan.words;
+        t.plan_ms = 1e3 * (r->t_queued - r->t_submit);
+        const double issued = r->t_issue > 0 ? r->t_issue : r->t_done;
+        t.wait_ms = 1e3 * (issued - r->t_queued);
+        t.run_ms = 1e3 * (r->t_done - issued);
+        S->timings.push_back(t);
+        if (S->timings.size() > TIMINGS_KEPT) S->timings.pop_front();
     }
     r->plan = Plan{};   // keep only the outcome
     r->items.clear();
@@ -524,6 +558,19 @@ void scheduler(ld_server* S)
             auto any_work = [&]() { return work_left(BULK) || work_left(EXPRESS); };
             poll_done(S);
             if (busy_all() == 0) {
+                if (!S->stop && !any_work() && S->idle_spin_s > 0) {
+                    // Idle.  A thread woken from a condition variable starts tens to
+                    // hundreds of microseconds later, which a small request would pay
+                    // on top of its own run time; so watch the arrival count first and
+                    // sleep only after idle_spin_s without one.
+                    const uint64_t seen = S->arrivals.load(std::memory_order_acquire);
+                    lk.unlock();
+                    const double t0 = now_s();
+                    while (S->arrivals.load(std::memory_order_acquire) == seen &&
+                           !S->stopping.load(std::memory_order_acquire) && now_s() - t0 < S->idle_spin_s)
+                        std::this_thread::yield();
+                    lk.lock();
+                }
                 S->cv.wait(lk, [&]() { return S->stop || any_work(); });
                 if (S->stop && !any_work()) return;
             }
@@ -574,9 +621,12 @@ ld_server* ld_server_create(const ld_server_config* cfg_in)
     if (cfg.step_ms <= 0) cfg.step_ms = 4.0;
     if (cfg.express_ms == 0) cfg.express_ms = 1.0;
     if (cfg.max_queued <= 0) cfg.max_queued = 65536;
+    if (cfg.idle_spin_ms == 0) cfg.idle_spin_ms = 1e3 * IDLE_SPIN_S;
+    if (cfg.min_items == 0) cfg.min_items = (int32_t)SERVE_MIN_ITEMS;
     ld_server* S = new ld_server;
     S->cfg = cfg;
     S->express_cost = COST_UNITS_PER_S * cfg.express_ms * 1e-3;
+    S->idle_spin_s = std::max(0.0, cfg.idle_spin_ms * 1e-3);
     S->device = cfg.device;
     int count = 0;
     bool ok = hipGetDeviceCount(&count) == hipSuccess && cfg.device >= 0 && cfg.device < count &&
@@ -678,9 +728,16 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
             ItemShape ish;
             ish.item_words = S->cfg.words_per_item;
             ish.max_items = 1u << 16;
+            // a small request's items spread over the device (one per resident wave or
+            // so) instead of a few waves each sweeping many prefixes
+            ish.min_items = (uint32_t)std::max(0, S->cfg.min_items);
             std::vector<std::pair<double, Item>> its;
             split_items(r->plan, 0, ish, its);
-            std::stable_sort(its.begin(), its.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+            // split_items cuts equal items in prefix order, the last one possibly
+            // shorter: the list is already longest first, so no sort (a large request
+            // has up to 2^16 items, and this runs on the submitting thread)
+            r->items.reserve(its.size());
+            r->cost.reserve(its.size());
             for (auto& c : its) {
                 r->items.push_back(c.second);
                 r->cost.push_back(c.first);
@@ -690,6 +747,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         if (align256(r->plan.blob.size()) > S->cfg.arena_bytes) r->plan.status = LD_ETOOBIG;
         r->lane = (S->cfg.express_ms > 0 && (r->is_sum || r->remaining < S->express_cost)) ? EXPRESS : BULK;
     }
+    r->t_queued = now_s();
     std::lock_guard<std::mutex> g(S->mu);
     if (S->failed) {
         delete r;
@@ -717,7 +775,10 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         finish(S, r, LD_OK, 0);
         return LD_OK;
     }
+    S->plan_sum_ms += 1e3 * (r->t_queued - r->t_submit);
+    S->plan_n++;
     S->lanes[r->lane].pending.push_back(r);
+    S->arrivals.fetch_add(1, std::memory_order_release);
     S->cv.notify_one();
     return LD_OK;
 }
@@ -796,6 +857,20 @@ void ld_server_stats(ld_server* S, ld_stats* out)
         out->mean_ms = s / v.size();
     }
     if (S->wait_n) out->mean_wait_ms = S->wait_sum_ms / (double)S->wait_n;
+    if (S->plan_n) out->mean_plan_ms = S->plan_sum_ms / (double)S->plan_n;
+    if (S->run_n) out->mean_run_ms = S->run_sum_ms / (double)S->run_n;
+}
+
+int32_t ld_server_timings(ld_server* S, ld_request_timing* out, int32_t max)
+{
+    if (!S) return -1;
+    std::lock_guard<std::mutex> g(S->mu);
+    int32_t n = 0;
+    for (const ld_request_timing& t : S->timings) {
+        if (n >= max || !out) break;
+        out[n++] = t;
+    }
+    return n;
 }
 
 void ld_server_destroy(ld_server* S)
@@ -821,6 +896,7 @@ void ld_server_destroy(ld_server* S)
             }
         }
         S->stop = true;
+        S->stopping.store(true, std::memory_order_release);
     }
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();

@@ -220,11 +220,12 @@ int ld_autotune(const char* path, double budget_seconds)
     set_tuning(best);
 
     // plain calls: kernel variant (low rows of the SGPR-operand kernel, or the
-    // VGPR-operand kernel), lane range and words per prefix, timed on a 30 x 40
-    // and a 35 x 42 L1 problem (sum of the two times)
+    // VGPR-operand kernel), lane range and words per prefix, timed on a 38 x 38
+    // and a 35 x 42 L1 problem (sum of the two times; the first has rows enough
+    // that the upper lane bound decides its shape)
     {
         Rng r{0xca1};
-        std::vector<int32_t> A((size_t)30 * 40), B((size_t)35 * 42);
+        std::vector<int32_t> A((size_t)38 * 38), B((size_t)35 * 42);
         for (auto& v : A) v = r.uniform(-100, 100);
         for (auto& v : B) v = r.uniform(-100, 100);
         double bt = 1e30;
@@ -240,7 +241,7 @@ int ld_autotune(const char* path, double budget_seconds)
                         t.plain_p_target = p;
                         t.plain_c_goal = c;
                         set_tuning(t);
-                        const double dt = time_plain(A, 30, 40) + time_plain(B, 35, 42);
+                        const double dt = time_plain(A, 38, 38) + time_plain(B, 35, 42);
                         std::snprintf(buf, sizeof buf,
                                       ", {\"sgpr_r\": %d, \"p_min\": %d, \"plain_p\": %d, \"c_goal\": %d, \"ms\": %.3f}",
                                       sr, pm, p, c, 1e3 * dt);
@@ -254,21 +255,23 @@ int ld_autotune(const char* path, double budget_seconds)
     }
     set_tuning(best);
 
-    // plain calls, d >= 3: lane count, timed on an L_3 problem of 22 x 32 and an
-    // L_4 problem of 18 x 24 (sum of the two times)
+    // plain calls, d >= 3: lane count, timed on an L_3 problem of 24 x 32 and an
+    // L_4 problem of 20 x 24 (sum of the two times; both large enough that their
+    // plans can trade mid rows up to the largest candidate, where the end of the
+    // launch, a fraction of one item per wave, stops mattering)
     {
         Rng r{0xd3a};
-        std::vector<int32_t> A((size_t)22 * 32), B((size_t)18 * 24);
+        std::vector<int32_t> A((size_t)24 * 32), B((size_t)20 * 24);
         for (auto& v : A) v = r.uniform(-100, 100);
         for (auto& v : B) v = r.uniform(-100, 100);
         double bt = 1e30;
         Tuning bp = best;
-        for (int lanes : {1 << 17, 1 << 18, 1 << 19}) {
+        for (int lanes : {1 << 18, 1 << 19, 1 << 20, 1 << 21}) {
             if (now_s() > t_end) break;
             Tuning t = best;
             t.plain_dary_lanes = lanes;
             set_tuning(t);
-            const double dt = time_plain(A, 22, 32, 3) + time_plain(B, 18, 24, 4);
+            const double dt = time_plain(A, 24, 32, 3) + time_plain(B, 20, 24, 4);
             std::snprintf(buf, sizeof buf, ", {\"dary_lanes\": %d, \"ms\": %.3f}", lanes, 1e3 * dt);
             notes += buf;
             if (dt < bt) {

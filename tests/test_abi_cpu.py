@@ -209,6 +209,7 @@ def test_tuning_file_round_trip(tmp_path):
     path.write_text('{"bin_c_target": 10, "plain_p_target": 18, "plain_p_min": 12, "plain_c_goal": 14, '
                     '"sgpr_r": 4, "variant_l1_2": -1, "measured": []}')
     M = synth.config_42_l1(0)
+    p0 = L.plan(M, 1, 0)
     try:
         L.load_tuning(str(path))
         p = L.plan(M, 1, 0)
@@ -218,7 +219,7 @@ def test_tuning_file_round_trip(tmp_path):
     finally:
         L.load_tuning(L.TUNING_PATH)
     p = L.plan(M, 1, 0)
-    assert p["R"] == 5 and p["P"] == 20
+    assert (p["R"], p["P"], p["C"], p["kernel"]) == (p0["R"], p0["P"], p0["C"], p0["kernel"])
 
 
 def test_plan_dary_lane_trading():
@@ -257,10 +258,11 @@ def test_plan_kernel_family_and_mfma_selection():
     M = synth.config_42_l1(0)
     p = L.plan(M, 1, 0)
     assert p["kernel"] == 5 and p["R"] == 5
+    c0 = p["C"]
     try:
         L.set_sweep_shape(0, 0, -1, 0, 8, -1)
         p = L.plan(M, 1, 0)
-        assert p["kernel"] == 2 and p["R"] == 5 and p["C"] == 16
+        assert p["kernel"] == 2 and p["R"] == 5 and p["C"] == c0 and 1 <= c0 <= 16
         big = synth.matrix(4, 20, 20, -1000, 1000, "abi")      # deltas 2 * 1000 do not fit int8
         p = L.plan(big, 1, 0)
         assert p["kernel"] == 1 and p["R"] == 5
@@ -292,17 +294,28 @@ def test_batch_plan_dary_step_count_fits_32_bits(tmp_path):
 
 
 def test_error_strings_cover_every_code(lib):
-    texts = {code: lib.ld_error_string(code).decode() for code in range(9)}
+    texts = {code: lib.ld_error_string(code).decode() for code in range(10)}
     fallback = lib.ld_error_string(99).decode()
     assert fallback == "unknown error code"
     assert fallback not in texts.values(), texts
-    assert len(set(texts.values())) == 9
+    assert len(set(texts.values())) == 10
 
 
-def test_small_problems_take_lanes_before_mid_rows():
+def test_small_problems_take_lanes_before_mid_rows(tmp_path):
     """A small binary problem keeps 2^16 prefixes (one wave per SIMD) before any row
     becomes a mid row; mid rows beyond those go up to the usual minimum of four,
-    and large problems keep their shape."""
+    and large problems keep their shape (lane bounds 2^19 .. 2^20, 2^12 words per
+    prefix between them)."""
+    path = tmp_path / "shape.json"
+    path.write_text('{"plain_p_target": 20, "plain_p_min": 19, "plain_c_goal": 12, "measured": []}')
+    L.load_tuning(str(path))
+    try:
+        _check_small_problem_shapes()
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+
+
+def _check_small_problem_shapes():
     p = L.plan(synth.config_pm(0), 2, 0)              # 16 x 32 L2: every free row is a lane row
     assert p["R"] == 5 and p["C"] == 0 and p["P"] == 10, p
     p = L.plan(synth.config_pm24(0), 2, 0)            # 24 x 24 L2: 2^16 lanes, two mid rows

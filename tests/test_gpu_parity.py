@@ -508,10 +508,11 @@ def test_autotune_writes_table_and_keeps_values(tmp_path):
         L.autotune(path, 2.0)
         table = json.load(open(path))
         for key in ("bin_c_target", "dary_cwords", "item_words", "plain_p_target", "plain_c_goal", "sgpr_r",
-                    "plain_dary_lanes", "variant_l1_2", "measured"):
+                    "dary_variant", "plain_dary_lanes", "variant_l1_2", "measured"):
             assert key in table, key
         assert len(table["measured"]) >= 1
-        assert table["plain_dary_lanes"] in (0, 1 << 17, 1 << 18, 1 << 19)
+        assert table["plain_dary_lanes"] in (0, 1 << 18, 1 << 19, 1 << 20, 1 << 21)
+        assert table["dary_variant"] in (0, 1, 16) and table["sgpr_r"] in (0, 4, 5, 8, 16)
         assert [L.ld_norm(M, d, marg) for M, d, marg in probs] == before
         # the written table loads back and still gives the same values
         L.load_tuning(path)
