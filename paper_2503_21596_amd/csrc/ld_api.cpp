@@ -11,6 +11,7 @@
 #include "ld_plan.h"
 #include "ld_program.h"
 #include "ld_registry.h"
+#include "ld_tune.h"
 
 namespace ld {
 
@@ -37,6 +38,8 @@ namespace {
 struct Ctx {
     int device = -1;
     hipStream_t stream = nullptr;
+    std::vector<hipStream_t> side;   // launches of many-problem programs fan out over these
+    std::vector<hipEvent_t> fan_ev;
     void* dbuf = nullptr;
     size_t dcap = 0;
     void* hbuf = nullptr;
@@ -49,6 +52,10 @@ struct Ctx {
         if (dbuf) (void)hipFree(dbuf);
         if (hbuf) (void)hipHostFree(hbuf);
         if (hres) (void)hipHostFree(hres);
+        for (hipEvent_t e : fan_ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipStream_t s : side)
+            if (s) (void)hipStreamDestroy(s);
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
@@ -92,6 +99,22 @@ bool ensure(Ctx& c, size_t bytes, size_t nres)
 
 // Solve a set of planned problems synchronously on the calling thread's buffers.
 // out[i] receives problem i's value; problems with value 0 need no search.
+// the thread's side streams and fork/join events for fanned-out launches
+bool ensure_side(Ctx& c, int n)
+{
+    while ((int)c.side.size() < n) {
+        hipStream_t s2 = nullptr;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) return false;
+        c.side.push_back(s2);
+    }
+    while ((int)c.fan_ev.size() < n + 1) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+        c.fan_ev.push_back(e);
+    }
+    return true;
+}
+
 bool run_plans_sync(const std::vector<const Plan*>& plans, const ItemShape& shape, int64_t* out, hipStream_t s)
 {
     Ctx& c = t_ctx;
@@ -100,8 +123,13 @@ bool run_plans_sync(const std::vector<const Plan*>& plans, const ItemShape& shap
     if (!s) s = c.stream;
     patch_program(P, c.dbuf);
     std::memcpy(c.hbuf, P.image.data(), P.image.size());
+    // several kernel shapes: let their launches overlap on side streams
+    const int n_side = P.launches.size() > 1 ? batch_side_streams() : 0;
+    if (n_side > 0 && !ensure_side(c, n_side)) return false;
+    const std::vector<hipStream_t> side(c.side.begin(), c.side.begin() + n_side);
+    const std::vector<hipEvent_t> evs(c.fan_ev.begin(), c.fan_ev.begin() + (n_side > 0 ? n_side + 1 : 0));
     bool ok = hipMemcpyAsync(c.dbuf, c.hbuf, P.image.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && enqueue_program(P, s, c.hres);
+    ok = ok && enqueue_program_fanned(P, s, c.hres, side, evs);
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();

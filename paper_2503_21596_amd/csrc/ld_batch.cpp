@@ -55,6 +55,8 @@ struct ld_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipStream_t> side;   // launches fan out over these inside the graph
+    std::vector<hipEvent_t> fan_ev;
     float last_ms = 0.f;
 };
 
@@ -69,6 +71,10 @@ void release(ld_batch* b)
     if (b->hres) (void)hipHostFree(b->hres);
     if (b->e0) (void)hipEventDestroy(b->e0);
     if (b->e1) (void)hipEventDestroy(b->e1);
+    for (hipEvent_t e : b->fan_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->side)
+        if (s) (void)hipStreamDestroy(s);
     if (b->own) (void)hipStreamDestroy(b->own);
     delete b;
 }
@@ -151,9 +157,20 @@ ld_batch* ld_batch_prepare(const ld_problem* probs, int32_t count, int32_t* stat
     if (ok)
         for (const Launch& L : b->prog.launches) (void)capped_blocks(L.kernel, L.threads, L.lds);
     // capture reset + launches + result copy once; every run replays the graph
+    const int n_side = batch_side_streams();
+    for (int k = 0; ok && k < n_side; ++k) {
+        hipStream_t s2 = nullptr;
+        ok = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) == hipSuccess;
+        if (ok) b->side.push_back(s2);
+    }
+    for (int k = 0; ok && k <= n_side && n_side > 0; ++k) {
+        hipEvent_t e = nullptr;
+        ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) b->fan_ev.push_back(e);
+    }
     ok = ok && hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-        const bool enq = enqueue_program(b->prog, b->own, b->hres);
+        const bool enq = enqueue_program_fanned(b->prog, b->own, b->hres, b->side, b->fan_ev);
         ok = hipStreamEndCapture(b->own, &b->graph) == hipSuccess && enq;
     }
     ok = ok && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;

@@ -322,6 +322,12 @@ uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds)
 
 bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
 {
+    return enqueue_program_fanned(P, s, host_results, {}, {});
+}
+
+bool enqueue_program_fanned(const Program& P, hipStream_t s, int64_t* host_results,
+                            const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& evs)
+{
     uint8_t* dev = (uint8_t*)P.dev;
     int64_t* results = (int64_t*)(dev + P.off_results);
     uint32_t* heads = (uint32_t*)(dev + P.off_heads);
@@ -331,7 +337,25 @@ bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
         void* args[] = {(void*)&results, (void*)&nr, (void*)&heads, (void*)&nh};
         if (hipLaunchKernel(kernel_reset(), dim3(blocks), dim3(256), args, 0, s) != hipSuccess) return false;
     }
+    // Fan the launches out over the side streams: each waits for the reset, takes
+    // launches greedily by estimated work (most work first), and the main stream
+    // waits for all of them before the result copy.  Launches of different kernel
+    // shapes share no queue head and no problem, so they may overlap; one that
+    // drains its queue leaves its CUs to the others instead of to nothing.
+    const bool fan = !side.empty() && evs.size() >= side.size() + 1 && P.launches.size() > 1;
+    std::vector<hipStream_t> lanes{s};
+    if (fan) {
+        if (hipEventRecord(evs[0], s) != hipSuccess) return false;
+        for (size_t k = 0; k < side.size(); ++k) {
+            if (hipStreamWaitEvent(side[k], evs[0], 0) != hipSuccess) return false;
+            lanes.push_back(side[k]);
+        }
+    }
+    std::vector<double> load(lanes.size(), 0.0);
     for (const Launch& L : P.launches) {
+        const size_t li = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[li] += L.cost;
+        hipStream_t ls = lanes[li];
         QArgs q{};
         q.descs = (const Desc*)(dev + P.off_descs);
         q.items = L.implicit ? nullptr : (const Item*)(dev + L.off_items);
@@ -344,8 +368,13 @@ bool enqueue_program(const Program& P, hipStream_t s, int64_t* host_results)
         const uint32_t want = (L.n_items + waves_per_block - 1) / waves_per_block;
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, capped_blocks(L.kernel, L.threads, L.lds)));
         void* args[] = {(void*)&q};
-        if (hipLaunchKernel(L.kernel, dim3(blocks), dim3(L.threads), args, L.lds, s) != hipSuccess) return false;
+        if (hipLaunchKernel(L.kernel, dim3(blocks), dim3(L.threads), args, L.lds, ls) != hipSuccess) return false;
     }
+    if (fan)
+        for (size_t k = 0; k < side.size(); ++k) {
+            if (hipEventRecord(evs[k + 1], side[k]) != hipSuccess) return false;
+            if (hipStreamWaitEvent(s, evs[k + 1], 0) != hipSuccess) return false;
+        }
     if (P.n_sums) {
         const SumItem* items = (const SumItem*)(dev + P.off_sums);
         uint32_t ns = P.n_sums;

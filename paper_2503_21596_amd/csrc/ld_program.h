@@ -92,6 +92,11 @@ void patch_program(Program& prog, void* dev);
 // Enqueue: reset of heads and results, every launch, and the copy of the results
 // to host_results (pinned, n_probs int64).  Nothing here allocates.
 bool enqueue_program(const Program& prog, hipStream_t s, int64_t* host_results);
+// The same with the launches spread over the side streams (fork after the reset,
+// join before the copy); evs holds side.size() + 1 events.  Also valid under
+// stream capture, where the forks and joins become graph edges.
+bool enqueue_program_fanned(const Program& prog, hipStream_t s, int64_t* host_results,
+                            const std::vector<hipStream_t>& side, const std::vector<hipEvent_t>& evs);
 
 // Blocks per launch that fill the device once for a kernel (occupancy x CUs).
 uint32_t resident_blocks(const void* kernel, uint32_t threads, size_t lds);

@@ -109,9 +109,11 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
                  "  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
                  "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"dary_variant\": %d,\n"
-                 "  \"plain_p_min\": %d,\n  \"plain_dary_lanes\": %d,\n  \"measured\": [%s]\n}\n",
+                 "  \"plain_p_min\": %d,\n  \"plain_dary_lanes\": %d,\n  \"batch_side_streams\": %d,\n"
+                 "  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
-                 t.plain_r_drop, t.sgpr_r, t.dary_variant, t.plain_p_min, t.plain_dary_lanes, notes.c_str());
+                 t.plain_r_drop, t.sgpr_r, t.dary_variant, t.plain_p_min, t.plain_dary_lanes, t.batch_side_streams,
+                 notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -166,6 +168,8 @@ SweepShape batch_shape_for(int n, int m, int d)
     return s;
 }
 
+int batch_side_streams() { return std::max(0, std::min(7, get_tuning().batch_side_streams)); }
+
 ItemShape batch_item_shape()
 {
     ItemShape s;
@@ -217,6 +221,23 @@ int ld_autotune(const char* path, double budget_seconds)
                     best = t;
                 }
             }
+    set_tuning(best);
+
+    // batch launches fanned out over side streams (the launches of different kernel
+    // shapes overlap, so one that drains its queue leaves its CUs to the others)
+    for (int k : {0, 1, 3}) {
+        if (now_s() > t_end) break;
+        Tuning t = best;
+        t.batch_side_streams = k;
+        set_tuning(t);
+        const double dt = time_batch(cal);
+        std::snprintf(buf, sizeof buf, ", {\"batch_side_streams\": %d, \"ms\": %.3f}", k, 1e3 * dt);
+        notes += buf;
+        if (dt < best_t) {
+            best_t = dt;
+            best = t;
+        }
+    }
     set_tuning(best);
 
     // plain calls: kernel variant (low rows of the SGPR-operand kernel, or the
@@ -363,6 +384,7 @@ int ld_load_tuning(const char* path)
         t.sgpr_r = (v == 4 || v == 5 || v == VARIANT_MFMA || v == VARIANT_PACK16) ? (int)v : 0;
     if (read_key(text, "dary_variant", &v))
         t.dary_variant = v == VARIANT_PACK16 ? VARIANT_PACK16 : v != 0 ? 1 : 0;
+    if (read_key(text, "batch_side_streams", &v)) t.batch_side_streams = std::max(0, std::min(7, (int)v));
     if (read_key(text, "plain_dary_lanes", &v)) t.plain_dary_lanes = (int)std::max(0.0, std::min(v, 1073741824.0));
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < 4; ++b) {

@@ -19,6 +19,9 @@ struct Tuning {
     int dary_variant = 16;        // int32 d = 3, 4: 16 packed where it fits, 1 SGPR operands, 0 VGPR
     int plain_dary_lanes = 1 << 19;  // plain calls, d >= 3: trade mid rows for prefix rows until
                                      // this many lanes exist
+    int batch_side_streams = 3;      // batches: launches fan out over this many extra streams
+                                     // (inside the captured graph for batch handles; 0: one
+                                     // chain of launches)
     // kernel variant per (kind class, width bucket), as SweepShape::variant (-1: the above)
     int variant[4][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
 };
@@ -31,5 +34,8 @@ SweepShape batch_shape_for(int n, int m, int d);
 
 // queue-item shape of a batch
 ItemShape batch_item_shape();
+
+// extra streams a batch's launches fan out over
+int batch_side_streams();
 
 }  // namespace ld

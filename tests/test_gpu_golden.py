@@ -99,3 +99,24 @@ def test_serve_members_in_the_mix():
             time.sleep(0.0005)
         for t, want, tag in tickets:
             assert S.wait(t) == want, tag
+
+
+BATCH_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_seed0.json")
+
+
+def test_full_batch_every_problem_against_oracle():
+    """Every one of the 4096 problems of the batch workload, through a plain batch
+    call and through a prepared batch replayed from its HIP graph, against the
+    oracle's values (tests/golden/batch_seed0.json, written by
+    tests/golden/make_batch_golden.py from oracle/ only)."""
+    g = json.load(open(BATCH_GOLDEN))
+    assert g["count"] == 4096 and len(g["values"]) == 4096
+    probs = synth.batch_problems(0, 4096)
+    say("full batch vs oracle")
+    assert [int(v) for v in L.ld_norm_batch(probs)] == g["values"]
+    B = L.Batch(probs)
+    try:
+        for _ in range(2):
+            assert [int(v) for v in B.run()] == g["values"]
+    finally:
+        B.close()

@@ -529,3 +529,20 @@ def test_ld_classes_planted(d):
     M = (K * H[t] + rnd(d + 90, n, m, -2, 2)).astype(np.int32)
     want = int(sum(np.abs(M[t == k].astype(np.int64).sum(axis=0)).sum() for k in range(d)))
     assert oracle.ld_classes(M, d) == want
+
+
+def test_batch_golden_matches_the_generator():
+    """tests/golden/batch_seed0.json holds the oracle's value of every batch problem:
+    a sample of the cheap members, recomputed here by the naive enumeration, agrees
+    (so the file belongs to the current generator and split-table forms)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_seed0.json")
+    g = json.load(open(path))
+    assert g["count"] == 4096 and len(g["values"]) == 4096
+    probs = synth.batch_problems(0, 4096)
+    cheap = [i for i, (M, d, marg) in enumerate(probs) if (d <= 2 and M.shape[0] <= 15) or (d == 3 and M.shape[0] <= 11)]
+    assert len(cheap) >= 100
+    for i in cheap[::len(cheap) // 40]:
+        M, d, marg = probs[i]
+        assert g["values"][i] == oracle.norm(M, d, marg), i
