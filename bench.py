@@ -113,12 +113,15 @@ def bench_batch(L, synth, seed: int = 0):
             "identical": bool(list(out) == plain and list(rep) == plain)}
 
 
-def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0):
+def bench_serve(L, synth, seed: int = 0, rate: float = 200.0, seconds: float = 30.0, warm_s: float = 5.0):
     """Poisson request stream into the server (continuous batching) against the same
     trace replayed in real time through sequential plain calls (first come, first
-    served, so queueing is included)."""
+    served, so queueing is included).  The trace lasts warm_s + seconds; latencies
+    count the requests that arrive after the first warm_s seconds."""
     import numpy as np
+    count = int(round(rate * (seconds + warm_s)))
     reqs = synth.served_requests(seed, count=count, rate=rate)
+    warm = sum(1 for t, _, _ in reqs if t < warm_s)
     S = L.Server()
     tickets = []
     t_start = time.perf_counter()
@@ -130,17 +133,18 @@ def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0)
     vals = [S.wait(t) for t in tickets]
     t_end = time.perf_counter()
     st = S.stats()
-    tm = S.timings()
+    tm = {t["ticket"]: t for t in S.timings()}
     S.close()
-    served = {"requests": count, "rate_per_s": rate, "solves_per_s": count / (t_end - t_start),
-              "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-              "mean_wait_ms": st["mean_wait_ms"], "mean_plan_ms": st["mean_plan_ms"],
-              "mean_run_ms": st["mean_run_ms"], "launches": st["launches"],
+    tm = [tm[t] for t in tickets[warm:]]
+    lat = np.array([t["plan_ms"] + t["wait_ms"] + t["run_ms"] for t in tm])
+    served = {"requests": count, "warmup_requests": warm, "rate_per_s": rate,
+              "solves_per_s": count / (t_end - t_start),
+              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+              "mean_ms": float(lat.mean()), "launches": st["launches"],
               # medians of the latency split (plan: submitting thread; wait: until the first
               # step with the request's items is issued; run: from there to completion)
-              "p50_split_ms": {k: float(np.median([t[k] for t in tm])) for k in ("plan_ms", "wait_ms", "run_ms")}
-              if tm else None,
-              "express_share": float(np.mean([t["lane"] for t in tm])) if tm else None}
+              "p50_split_ms": {k: float(np.median([t[k] for t in tm])) for k in ("plan_ms", "wait_ms", "run_ms")},
+              "express_share": float(np.mean([t["lane"] for t in tm]))}
     # the same trace in real time through sequential plain calls: one thread waits
     # for each arrival (when idle) and serves the requests first come, first served
     durs = []
@@ -157,7 +161,7 @@ def bench_serve(L, synth, seed: int = 0, count: int = 2000, rate: float = 200.0)
         durs.append(t1 - t0)
         lat.append(t1 - (t_start + t_arr))
     t_end = time.perf_counter()
-    lat = np.array(lat) * 1e3
+    lat = np.array(lat[warm:]) * 1e3
     seq = {"solves_per_s": count / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50)),
            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "busy_s": float(sum(durs))}
     return {"served": served, "sequential_plain": seq, "identical": vals == seq_vals,
@@ -478,7 +482,7 @@ def main():
         out["batched_vs_plain"] = bench_batch(L, synth)
         print("bench: serve", file=sys.stderr, flush=True)
         out["served"] = bench_serve(L, synth)
-        out["served_600"] = bench_serve(L, synth, seed=1, count=3000, rate=600.0)
+        out["served_600"] = bench_serve(L, synth, seed=1, rate=600.0, seconds=10.0, warm_s=2.0)
         out["served_burst"] = bench_serve_burst(L, synth)
         Mm = synth.config_42_marg(0)
         hm = L.Prepared(Mm, 1, 1)

@@ -55,7 +55,7 @@ double word_cost(const Plan& p)
     }
 }
 
-void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<std::pair<double, Item>>& out)
+uint64_t item_prefixes(const Plan& p, const ItemShape& sh)
 {
     const bool wide = p.wide != 0;
     const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);   // words per prefix
@@ -81,16 +81,29 @@ void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<
         per = std::min<uint64_t>(per, unit * kmax);
     }
     per = std::max<uint64_t>(per, (p.n_prefix + sh.max_items - 1) / sh.max_items);
-    per = std::min<uint64_t>(per, 0xffffffffull);
+    return std::min<uint64_t>(per, 0xffffffffull);
+}
+
+double item_cost(const Plan& p, uint64_t count)
+{
+    const double wpp = p.words / (double)std::max<uint64_t>(p.n_prefix, 1);
+    // a register-kernel wave covers 64 prefixes per round, each lane one word of
+    // them per step; an MFMA-kernel wave covers two prefixes, 64 words per step
+    const double rounds = p.wide ? (double)count : p.mfma ? std::ceil(count / 2.0) / 32.0 : std::ceil(count / 64.0);
+    return rounds * wpp * word_cost(p);
+}
+
+void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<std::pair<double, Item>>& out)
+{
+    const uint64_t per = item_prefixes(p, sh);
+    const double full = item_cost(p, per);
+    if (out.empty()) out.reserve((size_t)((p.n_prefix + per - 1) / per));
     for (uint64_t p0 = 0; p0 < p.n_prefix; p0 += per) {
         Item it;
         it.prob = prob;
         it.count = (uint32_t)std::min<uint64_t>(per, p.n_prefix - p0);
         it.p0 = p0;
-        // a register-kernel wave covers 64 prefixes per round, each lane one word
-        // of them per step; an MFMA-kernel wave covers two prefixes, 64 words per step
-        const double rounds = wide ? it.count : p.mfma ? std::ceil(it.count / 2.0) / 32.0 : std::ceil(it.count / 64.0);
-        out.push_back({rounds * wpp * word_cost(p), it});
+        out.push_back({it.count == per ? full : item_cost(p, it.count), it});
     }
 }
 

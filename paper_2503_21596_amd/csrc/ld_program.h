@@ -68,9 +68,16 @@ inline ItemShape plain_item_shape()
     return s;
 }
 
+// Prefixes per queue item of a problem cut with shape `sh` (all items but the last
+// hold that many; the last holds the rest).
+uint64_t item_prefixes(const Plan& p, const ItemShape& sh);
+// Estimated cost of an item of `count` prefixes: lane-level VALU instructions of one
+// lane of the wave that sweeps it.
+double item_cost(const Plan& p, uint64_t count);
 // Split one problem's prefix space into queue items (tagged with problem index
-// `prob`), each with its estimated VALU cost.  `wide` items are swept by one wave
-// prefix after prefix; register-kernel items put one prefix on each lane.
+// `prob`), each with its estimated VALU cost, in prefix order.  `wide` items are
+// swept by one wave prefix after prefix; register-kernel items put one prefix on
+// each lane.
 void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<std::pair<double, Item>>& out);
 
 // estimated VALU operations per word of a planned problem

@@ -85,9 +85,12 @@ struct Request {
     int slot = -1;
     size_t arena_off = 0, arena_size = 0;
     bool tracked = false;            // completes through its host-mapped record
-    std::vector<Item> items;         // sorted longest first
-    std::vector<double> cost;
-    size_t next = 0;                 // first item not yet issued
+    // queue items, implicit: item k holds prefixes [k per, min((k + 1) per, n_prefix)),
+    // all but the last one the same length, so issuing them in order is longest first
+    uint32_t n_items = 0;
+    uint64_t per = 0;
+    double cost_full = 0, cost_last = 0;
+    uint32_t next = 0;               // first item not yet issued
     double remaining = 0;            // estimated cost of the items not yet issued
     uint32_t outstanding = 0;        // issued items, plus the admission, whose step has not retired
     bool canceled = false;
@@ -229,7 +232,7 @@ void finish(ld_server* S, Request* r, int status, int64_t value)
         ld_request_timing t{};
         t.ticket = r->ticket;
         t.lane = r->lane;
-        t.items = (int32_t)r->items.size();
+        t.items = (int32_t)r->n_items;
         t.words = r->plan.words;
         t.plan_ms = 1e3 * (r->t_queued - r->t_submit);
         const double issued = r->t_issue > 0 ? r->t_issue : r->t_done;
@@ -239,10 +242,6 @@ void finish(ld_server* S, Request* r, int status, int64_t value)
         if (S->timings.size() > TIMINGS_KEPT) S->timings.pop_front();
     }
     r->plan = Plan{};   // keep only the outcome
-    r->items.clear();
-    r->items.shrink_to_fit();
-    r->cost.clear();
-    r->cost.shrink_to_fit();
     S->done_cv.notify_all();
 }
 
@@ -274,7 +273,7 @@ bool retire(ld_server* S, Lane& L)
         for (auto& [r, n] : st.issued) {
             r->outstanding -= n;
             // (a request that completed through its record has no items left)
-            if (r->outstanding == 0 && r->next >= r->items.size() && r->slot >= 0) {
+            if (r->outstanding == 0 && r->next >= r->n_items && r->slot >= 0) {
                 const int slot = r->slot;
                 const int64_t v = st.hres[slot];
                 release_slot(S, r);
@@ -325,7 +324,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         // 3. items: smallest remaining work first, up to the step budget
         std::vector<Request*> live;
         for (Request* r : S->slots)
-            if (r && r->lane == li && r->next < r->items.size()) live.push_back(r);
+            if (r && r->lane == li && r->next < r->n_items) live.push_back(r);
         std::sort(live.begin(), live.end(), [](Request* a, Request* b) { return a->remaining < b->remaining; });
         // a long bulk queue (saturation) gets steps twice as long: fewer steps, less
         // per-step overhead; the express lane keeps small requests responsive
@@ -340,12 +339,15 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         for (Request* r : live) {
             if (used >= budget || n_items >= (size_t)S->cfg.max_items_per_launch) break;
             std::vector<Item> take;
-            while (r->next < r->items.size() && (take.empty() || used < budget) &&
+            while (r->next < r->n_items && (take.empty() || used < budget) &&
                    n_items < (size_t)S->cfg.max_items_per_launch) {
-                Item it = r->items[r->next];
+                Item it;
                 it.prob = (uint32_t)r->slot;
-                used += r->cost[r->next];
-                r->remaining -= r->cost[r->next];
+                it.p0 = (uint64_t)r->next * r->per;
+                it.count = (uint32_t)std::min<uint64_t>(r->per, r->plan.n_prefix - it.p0);
+                const double c = r->next + 1 == r->n_items ? r->cost_last : r->cost_full;
+                used += c;
+                r->remaining -= c;
                 ++r->next;
                 take.push_back(it);
                 ++n_items;
@@ -430,7 +432,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         ops.push_back({D + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
         const uint32_t slot = (uint32_t)r->slot;
         std::memcpy(H + off_slots + 4 * k, &slot, 4);
-        const uint32_t count = r->is_sum ? 0u : (uint32_t)r->items.size();
+        const uint32_t count = r->is_sum ? 0u : r->n_items;
         std::memcpy(H + off_counts + 4 * k, &count, 4);
         // the completion record starts clear (nothing can write it: the slot was free)
         __atomic_store_n(&S->done_host[slot].flag, 0u, __ATOMIC_RELEASE);
@@ -552,7 +554,7 @@ void scheduler(ld_server* S)
             auto work_left = [&](int li) {
                 if (!S->lanes[li].pending.empty() && !S->free_slots.empty()) return true;
                 for (Request* r : S->slots)
-                    if (r && r->lane == li && r->next < r->items.size()) return true;
+                    if (r && r->lane == li && r->next < r->n_items) return true;
                 return false;
             };
             auto any_work = [&]() { return work_left(BULK) || work_left(EXPRESS); };
@@ -580,7 +582,7 @@ void scheduler(ld_server* S)
             // the running one, so that the device never waits for the host
             size_t bulk_live = S->lanes[BULK].pending.size();
             for (Request* r : S->slots)
-                if (r && r->lane == BULK && r->next < r->items.size()) ++bulk_live;
+                if (r && r->lane == BULK && r->next < r->n_items) ++bulk_live;
             bulk_depth = bulk_live > 16 ? 2 : S->bulk_depth;
         }
         bool ok = true, issued = false;
@@ -731,17 +733,14 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
             // a small request's items spread over the device (one per resident wave or
             // so) instead of a few waves each sweeping many prefixes
             ish.min_items = (uint32_t)std::max(0, S->cfg.min_items);
-            std::vector<std::pair<double, Item>> its;
-            split_items(r->plan, 0, ish, its);
-            // split_items cuts equal items in prefix order, the last one possibly
-            // shorter: the list is already longest first, so no sort (a large request
-            // has up to 2^16 items, and this runs on the submitting thread)
-            r->items.reserve(its.size());
-            r->cost.reserve(its.size());
-            for (auto& c : its) {
-                r->items.push_back(c.second);
-                r->cost.push_back(c.first);
-                r->remaining += c.first;
+            // the items stay implicit (a large request has up to 2^16 of them, and
+            // this runs on the submitting thread)
+            r->per = item_prefixes(r->plan, ish);
+            r->n_items = (uint32_t)((r->plan.n_prefix + r->per - 1) / r->per);
+            if (r->n_items > 0) {
+                r->cost_full = item_cost(r->plan, r->per);
+                r->cost_last = item_cost(r->plan, r->plan.n_prefix - (uint64_t)(r->n_items - 1) * r->per);
+                r->remaining = r->cost_full * (r->n_items - 1) + r->cost_last;
             }
         }
         if (align256(r->plan.blob.size()) > S->cfg.arena_bytes) r->plan.status = LD_ETOOBIG;
@@ -825,7 +824,7 @@ int ld_server_cancel(ld_server* S, uint64_t ticket)
     // items have retired
     r->canceled = true;
     r->remaining = 0;
-    r->next = r->items.size();
+    r->next = r->n_items;
     if (r->outstanding == 0) {
         release_slot(S, r);
         finish(S, r, LD_ECANCELED, INT64_MIN);
@@ -888,7 +887,7 @@ void ld_server_destroy(ld_server* S)
         for (Request* r : S->slots) {
             if (!r) continue;
             r->canceled = true;
-            r->next = r->items.size();
+            r->next = r->n_items;
             r->remaining = 0;
             if (r->outstanding == 0) {   // admitted, nothing issued: done now
                 release_slot(S, r);
