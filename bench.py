@@ -43,14 +43,16 @@ def scoring_ops_per_word(kind: str, m: int) -> int:
     raise ValueError(kind)
 
 
-KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip"]
+KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip",
+                  "paper_2503_21596_amd/csrc/ld_registry.h"]
 HEADLINE_PROFILE = "profiles/k_bin16s_l1_42x42.md"
 
 
-def profile_fields(path: str = HEADLINE_PROFILE) -> dict:
+def profile_fields(path: str = HEADLINE_PROFILE, plan: dict | None = None) -> dict:
     """The `key: value` lines of a committed rocprofv3 summary, or {} when the kernel
-    sources changed after the profile was taken (its counters then describe another
-    kernel)."""
+    sources changed after the profile was taken, or the live plan's sweep shape
+    (R, C, P) differs from the profiled one: its counters then describe another
+    kernel or another launch."""
     import hashlib
     path = os.path.join(ROOT, path)
     if not os.path.exists(path):
@@ -62,6 +64,8 @@ def profile_fields(path: str = HEADLINE_PROFILE) -> dict:
             fields[k.strip()] = v.strip()
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
     if fields.get("kernel_source_sha256_16") != h[:16]:
+        return {}
+    if plan is not None and fields.get("plan_r_c_p") != "%d %d %d" % (plan["R"], plan["C"], plan["P"]):
         return {}
     return fields
 
@@ -413,7 +417,7 @@ def main():
     achieved = words * ops / (kavg / 1e3)
     # engine clock under a VALU-bound load, and the issue rate the chip sustains
     probe = L.valu_probe(200.0)
-    prof = profile_fields()
+    prof = profile_fields(plan=plan)
     valu_issue = None
     # the kernel's own clock from the profile (busy cycles per shader engine over its
     # time), else the probe's clock under its VALU load

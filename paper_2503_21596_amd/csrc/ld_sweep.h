@@ -409,18 +409,23 @@ struct Bin16S {
     __device__ static __forceinline__ void score(const uint32_t (&s)[MW], uint64_t ob, uint32_t& best)
     {
         if constexpr (KIND == KIND_L2) {
-            static_for<NW / 2>([&](auto h) {
-                constexpr int w = 2 * h;
+            // each accumulator runs through both message sides of its pattern, so the
+            // two halves of the score need no add
+            static_for<NW / 4>([&](auto g) {
+                constexpr int w = 4 * g;
                 uint32_t a[4] = {0, 0, 0, 0};
-                static_for<N8>([&](auto c) { chunk4<w, NW + w, w + 1, NW + w + 1, c>(s, ob, a); });
-                best = max(best, max(a[0] + a[1], a[2] + a[3]));
+                static_for<N8>([&](auto c) { chunk4<w, w + 1, w + 2, w + 3, c>(s, ob, a); });
+                static_for<N8>([&](auto c) { chunk4<NW + w, NW + w + 1, NW + w + 2, NW + w + 3, c>(s, ob, a); });
+                best = max(max(best, a[0]), a[1]);   // two v_max3 per four patterns
+                best = max(max(best, a[2]), a[3]);
             });
         } else {
             static_for<NW / 4>([&](auto g) {
                 constexpr int w = 4 * g;
                 uint32_t a[4] = {0, 0, 0, 0};
                 static_for<N8>([&](auto c) { chunk4<w, w + 1, w + 2, w + 3, c>(s, ob, a); });
-                best = max(max(best, max(a[0], a[1])), max(a[2], a[3]));
+                best = max(max(best, a[0]), a[1]);   // two v_max3 per four patterns
+                best = max(max(best, a[2]), a[3]);
             });
         }
     }
