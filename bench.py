@@ -43,9 +43,17 @@ def scoring_ops_per_word(kind: str, m: int) -> int:
     raise ValueError(kind)
 
 
-KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip",
-                  "paper_2503_21596_amd/csrc/ld_registry.h"]
+KERNEL_SOURCES = ["paper_2503_21596_amd/csrc/ld_sweep.h", "paper_2503_21596_amd/csrc/ld_kernels_bin.hip"]
+# the registry lines that shape the headline kernel (its low-row count)
+KERNEL_REGISTRY = ("paper_2503_21596_amd/csrc/ld_registry.h", "PACK16_R")
 HEADLINE_PROFILE = "profiles/k_bin16s_l1_42x42.md"
+
+
+def kernel_source_bytes() -> bytes:
+    """The headline kernel's sources, and the registry lines that set its shape."""
+    reg, key = KERNEL_REGISTRY
+    lines = [l for l in open(os.path.join(ROOT, reg), "rb").read().split(b"\n") if key.encode() in l]
+    return b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES) + b"\n".join(lines)
 
 
 def profile_fields(path: str = HEADLINE_PROFILE, plan: dict | None = None) -> dict:
@@ -62,7 +70,7 @@ def profile_fields(path: str = HEADLINE_PROFILE, plan: dict | None = None) -> di
         if ":" in line and not line.startswith(("|", " ", "#", "-")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
+    h = hashlib.sha256(kernel_source_bytes()).hexdigest()
     if fields.get("kernel_source_sha256_16") != h[:16]:
         return {}
     if plan is not None and fields.get("plan_r_c_p") != "%d %d %d" % (plan["R"], plan["C"], plan["P"]):

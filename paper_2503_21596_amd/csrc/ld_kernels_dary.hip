@@ -123,35 +123,62 @@ __global__ __launch_bounds__(256) void k_reset(int64_t* __restrict__ results, ui
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
 }
 
-// Server steps: copy newly admitted tables and descriptors from the step's
-// upload buffer to their arena / descriptor slots, one block per copy job.
-__global__ __launch_bounds__(256) void k_scatter(const ScatterOp* __restrict__ ops, uint32_t n)
+// dst[i] = src[i] for i < n, i = first, first + step, ...: up to four loads in
+// flight per thread before its stores
+__device__ __forceinline__ void copy16x4(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n,
+                                         uint64_t first, uint64_t step)
 {
-    for (uint32_t b = blockIdx.x; b < n; b += gridDim.x) {
-        const ScatterOp op = ops[b];
-        if ((((uintptr_t)op.src | (uintptr_t)op.dst | op.bytes) & 15) == 0) {
-            const uint4* src = (const uint4*)op.src;
-            uint4* dst = (uint4*)op.dst;
-            for (uint64_t i = threadIdx.x; i < op.bytes / 16; i += blockDim.x) dst[i] = src[i];
-        } else {
-            for (uint64_t i = threadIdx.x; i < op.bytes; i += blockDim.x) op.dst[i] = op.src[i];
-        }
+    for (uint64_t i = first; i < n; i += 4 * step) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * step < n) v[k] = src[i + k * step];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + k * step < n) dst[i + k * step] = v[k];
     }
 }
 
-// Server steps: result slots of newly admitted problems to INT64_MIN and their
-// unfinished-item counters to their item counts; the step's queue heads to 0.
-__global__ __launch_bounds__(256) void k_reset_slots(int64_t* __restrict__ results, const uint32_t* __restrict__ slots,
-                                                     const uint32_t* __restrict__ counts, uint32_t n_slots,
-                                                     uint32_t* __restrict__ left, uint32_t* __restrict__ heads,
-                                                     uint32_t n_heads)
+// Server steps, one launch at raised wave priority (as express sweeps: a step
+// shares each SIMD with the waves of a long bulk sweep).  Blocks [0, nops) each
+// copy one newly admitted table or descriptor from the step buffer in host memory
+// to its arena or descriptor slot; the blocks after them set the new problems'
+// result slots to INT64_MIN and their unfinished-item counters to their item
+// counts, and copy the rest of the step buffer (queue items with their zeroed
+// heads, sum jobs) to device memory.  Host memory is microseconds away, so no
+// thread waits on more than one load from it before its loads of data.
+__global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += stride) {
-        results[slots[i]] = INT64_MIN;
-        left[slots[i]] = counts[i];
+    __builtin_amdgcn_s_setprio(3);
+    if (blockIdx.x < a.nops) {
+        const uint32_t b = blockIdx.x;
+        const ScatterOp op = b < STAGE_INLINE ? a.iops[b] : a.ops[b];
+        if ((((uintptr_t)op.src | (uintptr_t)op.dst | op.bytes) & 15) == 0)
+            copy16x4((const uint4*)op.src, (uint4*)op.dst, op.bytes / 16, threadIdx.x, blockDim.x);
+        else
+            for (uint64_t i = threadIdx.x; i < op.bytes; i += blockDim.x) op.dst[i] = op.src[i];
+        return;
     }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_heads; i += stride) heads[i] = 0;
+    const uint32_t nb = gridDim.x - a.nops;
+    const uint32_t stride = nb * blockDim.x;
+    const uint32_t tid = (blockIdx.x - a.nops) * blockDim.x + threadIdx.x;
+    for (uint32_t i = tid; i < a.n_slots; i += stride) {
+        const uint32_t slot = i < STAGE_INLINE ? a.islots[i] : a.slots[i];
+        a.results[slot] = INT64_MIN;
+        a.left[slot] = i < STAGE_INLINE ? a.icounts[i] : a.counts[i];
+    }
+    copy16x4(a.copy_src, a.copy_dst, a.copy_n16, tid, stride);
+}
+
+// Server steps: every result slot to host memory after the step's sweeps, at
+// raised wave priority (as k_stage).
+__global__ __launch_bounds__(256) void k_publish(const int64_t* __restrict__ results, int64_t* __restrict__ out,
+                                                 uint32_t n)
+{
+    __builtin_amdgcn_s_setprio(3);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = results[i];
+    __threadfence_system();
 }
 
 // Locating a maximiser: *first = the smallest i < n with rec[i] == target (the
@@ -239,8 +266,8 @@ const void* kernel_dary64(int d, int mp)
 const void* kernel_sumabs_many() { return (const void*)&k_sumabs_many; }
 const void* kernel_wide() { return (const void*)&k_wide; }
 const void* kernel_reset() { return (const void*)&k_reset; }
-const void* kernel_scatter() { return (const void*)&k_scatter; }
-const void* kernel_reset_slots() { return (const void*)&k_reset_slots; }
+const void* kernel_stage() { return (const void*)&k_stage; }
+const void* kernel_publish() { return (const void*)&k_publish; }
 const void* kernel_first_equal() { return (const void*)&k_first_equal; }
 const void* kernel_set_u64() { return (const void*)&k_set_u64; }
 const void* kernel_signs() { return (const void*)&k_signs; }

@@ -83,11 +83,31 @@ void split_items(const Plan& p, uint32_t prob, const ItemShape& sh, std::vector<
 // estimated VALU operations per word of a planned problem
 double word_cost(const Plan& p);
 
-// copy jobs for k_scatter: bytes from src to dst, both device-visible
+// copy jobs of k_stage: bytes from src to dst, both device-visible
 struct ScatterOp {
     const uint8_t* src;
     uint8_t* dst;
     uint64_t bytes;
+};
+
+// One server step's staging (k_stage): pointers into the step buffer in host
+// memory (device view) and into device memory.  The first STAGE_INLINE copy jobs
+// and new slots travel in the arguments themselves, one host-memory round trip
+// fewer for a step that admits a few requests.
+constexpr uint32_t STAGE_INLINE = 4;
+struct StageArgs {
+    const ScatterOp* ops;       // host: copy jobs (tables and descriptors of new problems)
+    uint32_t nops;
+    uint32_t n_slots;           // new problems
+    const uint32_t* slots;      // host: their result slots
+    const uint32_t* counts;     // host: their item counts
+    int64_t* results;           // device: result slots
+    uint32_t* left;             // device: unfinished-item counters
+    const uint4* copy_src;      // host: queue items, heads and sum jobs of the step
+    uint4* copy_dst;            // device: where the step's launches read them
+    uint64_t copy_n16;          // 16-byte units
+    ScatterOp iops[STAGE_INLINE];          // ops[0 .. STAGE_INLINE)
+    uint32_t islots[STAGE_INLINE], icounts[STAGE_INLINE];
 };
 
 // Build the image and launches for the given plans (all with status LD_OK).

@@ -71,8 +71,8 @@ const void* kernel_dary64(int d, int mp);
 const void* kernel_sumabs_many();
 const void* kernel_wide();
 const void* kernel_reset();
-const void* kernel_scatter();
-const void* kernel_reset_slots();
+const void* kernel_stage();     // k_stage(StageArgs): server step staging
+const void* kernel_publish();   // k_publish(results, out, n): server step results to host memory
 const void* kernel_first_equal();
 const void* kernel_set_u64();
 const void* kernel_signs();

@@ -8,9 +8,13 @@
 //   2. admits queued requests while a result slot and arena bytes are free;
 //   3. picks items, smallest remaining work first, up to about step_ms of
 //      device work;
-//   4. enqueues: one upload of the step buffer (new tables, descriptors, items),
-//      a scatter kernel, a slot and head reset, one persistent queue launch per
-//      kernel shape, and the copy of all result slots to pinned memory.
+//   4. enqueues: one staging kernel that reads the step buffer (new tables,
+//      descriptors, items) from pinned host memory, puts tables and descriptors
+//      in place and resets the new result slots; one persistent queue launch per
+//      kernel shape; and a kernel that writes every result slot to pinned host
+//      memory.  The staging and result kernels raise their waves' priority, as
+//      express launches do, since a step shares the SIMDs with a long bulk
+//      sweep; runtime copies (kernels too) could not.
 // One bulk step and up to two express steps are in flight, so a request that
 // arrives while others run is swept in the next step.  Result slots keep partial
 // maxima between steps.  A bulk request completes when the step with its last
@@ -136,9 +140,11 @@ struct Arena {
 struct Step {
     hipEvent_t ev = nullptr;
     bool busy = false;
-    uint8_t* host = nullptr;      // pinned upload buffer
-    uint8_t* dev = nullptr;       // device copy of it
-    int64_t* hres = nullptr;      // pinned copy of every result slot after the step
+    uint8_t* host = nullptr;      // step buffer, pinned host memory the device reads directly
+    uint8_t* host_dev = nullptr;  // its device view
+    uint8_t* dev = nullptr;       // device copy of its items, heads and sum jobs
+    int64_t* hres = nullptr;      // every result slot after the step (pinned, written by k_publish)
+    int64_t* hres_dev = nullptr;  // its device view
     std::vector<std::pair<Request*, uint32_t>> issued;   // request, items in this step
 };
 
@@ -406,6 +412,9 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     off = align256(off + 4 * admitted.size());
     const size_t off_counts = off;
     off = align256(off + 4 * admitted.size());
+    // from here on the buffer is copied to device memory by k_stage (the launches
+    // pop its items and count on its heads); the part above is read in place
+    const size_t off_copy = off;
     std::vector<std::pair<size_t, size_t>> gpos;   // items offset, count per group
     for (auto& g : groups) {
         gpos.push_back({off, g.second.size()});
@@ -421,15 +430,16 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     }
 
     uint8_t* H = st.host;
+    uint8_t* HD = st.host_dev;
     uint8_t* D = st.dev;
     std::vector<ScatterOp> ops;
     for (size_t k = 0; k < admitted.size(); ++k) {
         Request* r = admitted[k];
         std::memcpy(H + blob_at[k], r->plan.blob.data(), r->plan.blob.size());
-        ops.push_back({D + blob_at[k], S->arena_dev + r->arena_off, (uint64_t)r->plan.blob.size()});
+        ops.push_back({HD + blob_at[k], S->arena_dev + r->arena_off, (uint64_t)r->plan.blob.size()});
         const Desc d = make_desc(r->plan, S->arena_dev + r->arena_off, S->d_results + r->slot);
         std::memcpy(H + desc_at[k], &d, sizeof(Desc));
-        ops.push_back({D + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
+        ops.push_back({HD + desc_at[k], (uint8_t*)(S->d_descs + r->slot), (uint64_t)sizeof(Desc)});
         const uint32_t slot = (uint32_t)r->slot;
         std::memcpy(H + off_slots + 4 * k, &slot, 4);
         const uint32_t count = r->is_sum ? 0u : r->n_items;
@@ -447,27 +457,33 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     std::memset(H + off_heads, 0, 4 * std::max<size_t>(groups.size(), 1));
     if (!sums.empty()) std::memcpy(H + off_sums, sums.data(), sizeof(SumItem) * sums.size());
 
-    // 4. enqueue
+    // 4. enqueue: staging (reads the step buffer in host memory), the queue
+    // launches, the sum jobs, the results to host memory
     hipStream_t s = L.stream;
-    bool ok = hipMemcpyAsync(D, H, off, hipMemcpyHostToDevice, s) == hipSuccess;
-    if (ok && !ops.empty()) {
-        const ScatterOp* dops = (const ScatterOp*)(D + off_ops);
-        uint32_t nops = (uint32_t)ops.size();
-        void* args[] = {(void*)&dops, (void*)&nops};
-        ok = hipLaunchKernel(kernel_scatter(), dim3(std::min<uint32_t>(nops, 1024)), dim3(256), args, 0, s) ==
-             hipSuccess;
-    }
     uint32_t* dheads = (uint32_t*)(D + off_heads);
-    if (ok && !admitted.empty()) {
-        const uint32_t* dslots = (const uint32_t*)(D + off_slots);
-        const uint32_t* dcounts = (const uint32_t*)(D + off_counts);
-        uint32_t ns = (uint32_t)admitted.size(), nh = 0;
-        int64_t* dres = S->d_results;
-        uint32_t* dleft = S->d_left;
-        void* args[] = {(void*)&dres, (void*)&dslots, (void*)&dcounts, (void*)&ns, (void*)&dleft, (void*)&dheads,
-                        (void*)&nh};
-        ok = hipLaunchKernel(kernel_reset_slots(), dim3(std::max<uint32_t>(1, std::min<uint32_t>(64, (ns + 255) / 256))),
-                             dim3(256), args, 0, s) == hipSuccess;
+    bool ok;
+    {
+        StageArgs a{};
+        a.ops = (const ScatterOp*)(HD + off_ops);
+        a.nops = (uint32_t)ops.size();
+        a.n_slots = (uint32_t)admitted.size();
+        a.slots = (const uint32_t*)(HD + off_slots);
+        a.counts = (const uint32_t*)(HD + off_counts);
+        a.results = S->d_results;
+        a.left = S->d_left;
+        a.copy_src = (const uint4*)(HD + off_copy);
+        a.copy_dst = (uint4*)(D + off_copy);
+        a.copy_n16 = (off - off_copy) / 16;
+        for (uint32_t k = 0; k < STAGE_INLINE && k < a.nops; ++k) a.iops[k] = ops[k];
+        for (uint32_t k = 0; k < STAGE_INLINE && k < a.n_slots; ++k) {
+            a.islots[k] = (uint32_t)admitted[k]->slot;
+            a.icounts[k] = admitted[k]->is_sum ? 0u : admitted[k]->n_items;
+        }
+        // one block per copy job, then blocks for the slots and the rest of the buffer
+        const uint64_t rest = std::min<uint64_t>(
+            512, std::max<uint64_t>({(a.copy_n16 + 1023) / 1024, ((uint64_t)a.n_slots + 255) / 256, 1}));
+        void* args[] = {(void*)&a};
+        ok = hipLaunchKernel(kernel_stage(), dim3((uint32_t)(a.nops + rest)), dim3(256), args, 0, s) == hipSuccess;
     }
     gi = 0;
     size_t n_items = 0;
@@ -491,14 +507,18 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         const uint32_t per_cu = S->cus > 0 ? resident / (uint32_t)S->cus : 0;
         uint32_t cap = resident;
         // express work takes one block per CU (at raised wave priority) while bulk
-        // steps run, the whole device otherwise.  Bulk work leaves one block per CU
-        // free for it: always when its kernel fits five or more per CU (a wave fewer
-        // per SIMD does not slow a VALU-bound sweep there, and an express request
-        // then never waits for a bulk step to drain), else while express work exists
+        // steps run, the whole device otherwise.  Bulk work leaves room for it:
+        // always when its kernel fits five or more per CU (a wave fewer per SIMD
+        // does not slow a VALU-bound sweep there, and an express request then never
+        // waits for a bulk step to drain), else while express work exists.  The room
+        // is one block per CU, and a bulk launch takes at most five per CU: bulk L2
+        // launches of six per CU (kernels rated at seven) held back express
+        // dispatches until the bulk launch drained, milliseconds later, while five
+        // per CU never did.
         if (li == EXPRESS) {
             if (busy_steps(S->lanes[BULK]) > 0) cap = std::min<uint32_t>(resident, std::max(S->cus, 1));
         } else if (per_cu >= 5 || (per_cu >= 3 && express_active)) {
-            cap = resident - (uint32_t)S->cus;
+            cap = std::min<uint32_t>(resident - (uint32_t)S->cus, 5u * (uint32_t)S->cus);
         }
         const uint32_t blocks = std::max<uint32_t>(1, std::min(want, cap));
         void* args[] = {(void*)&q};
@@ -513,7 +533,13 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
         ok = hipLaunchKernel(kernel_sumabs_many(), dim3(std::min<uint32_t>(n, 1024)), dim3(256), args, 0, s) ==
              hipSuccess;
     }
-    ok = ok && hipMemcpyAsync(st.hres, S->d_results, 8 * (size_t)max_slots, hipMemcpyDeviceToHost, s) == hipSuccess;
+    {
+        const int64_t* res = S->d_results;
+        int64_t* out = st.hres_dev;
+        uint32_t n = (uint32_t)max_slots;
+        void* args[] = {(void*)&res, (void*)&out, (void*)&n};
+        ok = ok && hipLaunchKernel(kernel_publish(), dim3((n + 255) / 256), dim3(256), args, 0, s) == hipSuccess;
+    }
     ok = ok && hipEventRecord(st.ev, s) == hipSuccess;
     {
         std::lock_guard<std::mutex> g(S->mu);
@@ -672,10 +698,13 @@ ld_server* ld_server_create(const ld_server_config* cfg_in)
     for (auto& ln : S->lanes)
     for (auto& st : ln.steps) {
         ok = ok && hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) == hipSuccess;
-        ok = ok && hipHostMalloc((void**)&st.host, S->step_bytes, hipHostMallocDefault) == hipSuccess;
-        ok = ok && hipMalloc((void**)&st.dev, S->step_bytes) == hipSuccess;
-        ok = ok && hipHostMalloc((void**)&st.hres, 8 * (size_t)cfg.max_inflight_problems, hipHostMallocDefault) ==
+        ok = ok && hipHostMalloc((void**)&st.host, S->step_bytes, hipHostMallocMapped | hipHostMallocCoherent) ==
                        hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void**)&st.host_dev, st.host, 0) == hipSuccess;
+        ok = ok && hipMalloc((void**)&st.dev, S->step_bytes) == hipSuccess;
+        ok = ok && hipHostMalloc((void**)&st.hres, 8 * (size_t)cfg.max_inflight_problems,
+                                 hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void**)&st.hres_dev, st.hres, 0) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();

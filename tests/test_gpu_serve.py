@@ -140,9 +140,11 @@ def test_serve_cancel_after_admission():
     mids = [synth.matrix(300 + i, 23, 30, -100, 100, "adm_mid") for i in range(24)]
     smalls = small_mix(6, 60)
     want_small = [oracle.norm(A, d, marg) for A, d, marg in smalls]
-    # tiny steps (a few mid requests each), express below 2 us of estimated work, and
-    # items of 2^26 words whatever the request size (no floor on the item count)
-    with L.Server(step_ms=0.01, express_ms=0.002, words_per_item=float(1 << 26), min_items=-1) as S:
+    # tiny steps (a few mid requests each), express below 1 us of estimated work (the
+    # mid requests, 2^22 words, estimate about 1.9 us and stay bulk; the small ones are
+    # express), and items of 2^26 words whatever the request size (no floor on the
+    # item count)
+    with L.Server(step_ms=0.01, express_ms=0.001, words_per_item=float(1 << 26), min_items=-1) as S:
         t_big = S.submit(big, 1, 0)
         time.sleep(0.005)                       # the first bulk step (one long item) runs
         # more than 16 live bulk requests: a second step is issued behind the first and
