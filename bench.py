@@ -353,6 +353,10 @@ def main():
     ap.add_argument("--small", action="store_true",
                     help="instead of the benchmark, run only the smaller workloads (20x20 L1, 16x32 at d = 2, "
                          "3, 4, 24x24 L2) and print their timings as one JSON line (for profiling)")
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="only the served trace at this rate (requests/s): server against sequential calls "
+                         "(for profiling)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark, time one solve each of L1, L2, L_3 and L_4 across lane "
                          "counts and waves per SIMD and print the table as one JSON line")
@@ -384,6 +388,11 @@ def main():
         return
     if a.small:
         print(json.dumps({"other_configs": bench_small_configs(L, synth, stream)}), flush=True)
+        return
+    if a.serve > 0:
+        warm = min(5.0, a.serve_seconds / 6)
+        print(json.dumps({"served": bench_serve(L, synth, seed=0 if a.serve == 200.0 else 1, rate=a.serve,
+                                                seconds=a.serve_seconds, warm_s=warm)}), flush=True)
         return
     if a.solve:
         d, n, m = (int(x) for x in a.solve.split(","))
