@@ -182,6 +182,10 @@ struct ld_server {
     std::vector<Request*> slots;
 
     std::mutex mu;
+    // API calls waiting for mu.  While steps are in flight the scheduler polls in a
+    // loop and takes mu on every pass; the mutex is not fair, so a call could wait
+    // milliseconds for it.  The scheduler lets waiting calls go first.
+    std::atomic<int> api_waiting{0};
     std::condition_variable cv;       // scheduler wake-up
     // submissions so far and the stop request, readable without mu: an idle
     // scheduler watches them for a while before it sleeps on cv
@@ -221,6 +225,25 @@ struct ld_server {
 };
 
 namespace {
+
+// mu for an API call: announced, so that the scheduler steps aside (scheduler_lock)
+struct ApiLock {
+    std::unique_lock<std::mutex> lk;
+    explicit ApiLock(ld_server* S) : lk(S->mu, std::defer_lock)
+    {
+        S->api_waiting.fetch_add(1, std::memory_order_relaxed);
+        lk.lock();
+        S->api_waiting.fetch_sub(1, std::memory_order_relaxed);
+    }
+};
+
+// mu for the scheduler thread, after any API call waiting for it (bounded, so that
+// a stream of calls cannot hold the scheduler off)
+std::unique_lock<std::mutex> scheduler_lock(ld_server* S)
+{
+    for (int k = 0; k < 256 && S->api_waiting.load(std::memory_order_relaxed) > 0; ++k) std::this_thread::yield();
+    return std::unique_lock<std::mutex>(S->mu);
+}
 
 // complete a request (mu held)
 void finish(ld_server* S, Request* r, int status, int64_t value)
@@ -275,7 +298,7 @@ bool retire(ld_server* S, Lane& L)
             if (q == hipErrorNotReady) return true;
             if (q != hipSuccess) return false;
         }
-        std::lock_guard<std::mutex> g(S->mu);
+        auto g = scheduler_lock(S);
         for (auto& [r, n] : st.issued) {
             r->outstanding -= n;
             // (a request that completed through its record has no items left)
@@ -307,7 +330,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     std::vector<std::pair<Request*, std::vector<Item>>> picks;
     bool express_active = false;
     {
-        std::lock_guard<std::mutex> g(S->mu);
+        auto g = scheduler_lock(S);
         // 2. admission by slot and arena space (FIFO; a request too big for the
         // free arena waits and holds back the ones behind it)
         while (!L.pending.empty() && !S->free_slots.empty()) {
@@ -542,7 +565,7 @@ bool issue_step(ld_server* S, int li, bool* issued_any)
     }
     ok = ok && hipEventRecord(st.ev, s) == hipSuccess;
     {
-        std::lock_guard<std::mutex> g(S->mu);
+        auto g = scheduler_lock(S);
         for (auto& [r, items] : picks) st.issued.push_back({r, r->is_sum ? 1u : (uint32_t)items.size()});
         for (Request* r : admitted) st.issued.push_back({r, 1u});   // the admission hold
         S->st_launches += groups.size() + (sums.empty() ? 0 : 1);
@@ -576,7 +599,7 @@ void scheduler(ld_server* S)
         bool have_work[2];
         int bulk_depth = S->bulk_depth;
         {
-            std::unique_lock<std::mutex> lk(S->mu);
+            std::unique_lock<std::mutex> lk = scheduler_lock(S);
             auto work_left = [&](int li) {
                 if (!S->lanes[li].pending.empty() && !S->free_slots.empty()) return true;
                 for (Request* r : S->slots)
@@ -776,7 +799,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
         r->lane = (S->cfg.express_ms > 0 && (r->is_sum || r->remaining < S->express_cost)) ? EXPRESS : BULK;
     }
     r->t_queued = now_s();
-    std::lock_guard<std::mutex> g(S->mu);
+    ApiLock g(S);
     if (S->failed) {
         delete r;
         set_error(LD_EHIP);
@@ -814,7 +837,7 @@ int ld_server_submit(ld_server* S, const ld_problem* p, uint64_t* ticket)
 int ld_server_poll(ld_server* S, uint64_t ticket, int64_t* value)
 {
     if (!S) return LD_EINVAL;
-    std::lock_guard<std::mutex> g(S->mu);
+    ApiLock g(S);
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return LD_ENOTFOUND;
     if (it->second->status == LD_PENDING) return LD_PENDING;
@@ -825,11 +848,11 @@ int ld_server_poll(ld_server* S, uint64_t ticket, int64_t* value)
 int ld_server_wait(ld_server* S, uint64_t ticket, int64_t* value)
 {
     if (!S) return LD_EINVAL;
-    std::unique_lock<std::mutex> lk(S->mu);
+    ApiLock g(S);
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return LD_ENOTFOUND;
     Request* r = it->second;
-    S->done_cv.wait(lk, [&]() { return r->status != LD_PENDING; });
+    S->done_cv.wait(g.lk, [&]() { return r->status != LD_PENDING; });
     if (value && r->status == LD_OK) *value = r->value;
     return r->status;
 }
@@ -837,7 +860,7 @@ int ld_server_wait(ld_server* S, uint64_t ticket, int64_t* value)
 int ld_server_cancel(ld_server* S, uint64_t ticket)
 {
     if (!S) return LD_EINVAL;
-    std::lock_guard<std::mutex> g(S->mu);
+    ApiLock g(S);
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return LD_ENOTFOUND;
     Request* r = it->second;
@@ -864,7 +887,7 @@ int ld_server_cancel(ld_server* S, uint64_t ticket)
 void ld_server_stats(ld_server* S, ld_stats* out)
 {
     if (!S || !out) return;
-    std::lock_guard<std::mutex> g(S->mu);
+    ApiLock g(S);
     std::memset(out, 0, sizeof(*out));
     out->submitted = S->st_submitted;
     out->completed = S->st_completed;
@@ -892,7 +915,7 @@ void ld_server_stats(ld_server* S, ld_stats* out)
 int32_t ld_server_timings(ld_server* S, ld_request_timing* out, int32_t max)
 {
     if (!S) return -1;
-    std::lock_guard<std::mutex> g(S->mu);
+    ApiLock g(S);
     int32_t n = 0;
     for (const ld_request_timing& t : S->timings) {
         if (n >= max || !out) break;
@@ -905,7 +928,7 @@ void ld_server_destroy(ld_server* S)
 {
     if (!S) return;
     {
-        std::lock_guard<std::mutex> g(S->mu);
+        ApiLock g(S);
         // queued requests are cancelled; in-flight ones finish their issued items
         for (auto& ln : S->lanes)
             while (!ln.pending.empty()) {
