@@ -27,7 +27,10 @@ UNITS = [
     ("ld_kernels_mfma.hip", ["-DLD_KIND=1"], "kmfma1.o"),
     ("ld_kernels_mfma.hip", ["-DLD_KIND=2"], "kmfma2.o"),
     ("ld_kernels_dary.hip", [], "kdary.o"),
-    ("ld_kernels_dary_s.hip", [], "kdarys.o"),
+    ("ld_kernels_dary_s.hip", ["-DLD_PART=0", "-DLD_NPARTS=4"], "kdarys0.o"),
+    ("ld_kernels_dary_s.hip", ["-DLD_PART=1", "-DLD_NPARTS=4"], "kdarys1.o"),
+    ("ld_kernels_dary_s.hip", ["-DLD_PART=2", "-DLD_NPARTS=4"], "kdarys2.o"),
+    ("ld_kernels_dary_s.hip", ["-DLD_PART=3", "-DLD_NPARTS=4"], "kdarys3.o"),
     ("ld_kernels_probe.hip", [], "kprobe.o"),
     ("ld_plan.cpp", [], "plan.o"),
     ("ld_program.cpp", [], "program.o"),

@@ -1,5 +1,7 @@
 // d-ary sweep kernels with the subset operands streamed through SGPRs (Dary32S),
-// for d = 3, 4; a compilation unit of their own so that the build runs in parallel.
+// for d = 3, 4.  Compiled as LD_NPARTS compilation units (-DLD_PART=0 ..
+// LD_NPARTS - 1), each instantiating every LD_NPARTS-th column count, so that the
+// build runs them in parallel; part 0 holds the tables and the lookups.
 #include <hip/hip_runtime.h>
 #include <utility>
 
@@ -23,10 +25,10 @@ constexpr int dary_s_waves(int mp, int d)
 // The same for the packed 16-bit kernels, by dword count W (two columns each):
 // the d vectors of W dwords, the 2^R subset scores of each message and the
 // temporaries.
-constexpr int dary16_waves(int w, int d)
+constexpr int dary16_waves(int w, int d, int r)
 {
-    if (d == 3) return w <= 20 ? 4 : 3;
-    return w <= 12 ? 4 : 3;
+    if (r == dary16_r(d)) return d == 3 ? (w <= 14 ? 3 : 2) : (w <= 12 ? 3 : 2);
+    return d == 3 ? (w <= 20 ? 4 : 3) : (w <= 12 ? 4 : 3);
 }
 
 // Persistent queue kernel (see k_bin32): one item = a range of prefixes of one
@@ -63,23 +65,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_wave
     dary_s_queue<Dary32S<MP, DD, DARY_RS>>(q);
 }
 
-template <int W, int DD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary16_waves(W, DD)))) void k_dary16s(QArgs q)
+template <int W, int DD, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary16_waves(W, DD, R)))) void k_dary16s(QArgs q)
 {
-    dary_s_queue<Dary32S<W, DD, dary16_r(DD), true>>(q);
+    dary_s_queue<Dary32S<W, DD, R, true>>(q);
 }
 
-namespace {
+#ifndef LD_PART
+#define LD_PART 0
+#define LD_NPARTS 1
+#endif
 
 constexpr int NMPD = MAX_MP / 4;   // mp = 4, 8, ..., 64
+// zero before any part's registration runs (constant initialisation)
+#if LD_PART == 0
 const void* g_dary32s[MAX_D + 1][NMPD] = {};
-const void* g_dary16s[MAX_D + 1][NMPD] = {};   // by dword count 2, 4, ..., 32
+const void* g_dary16s[2][MAX_D + 1][NMPD] = {};   // [larger R?][d][dword count 2, 4, ..., 32]
+#else
+extern const void* g_dary32s[MAX_D + 1][NMPD];
+extern const void* g_dary16s[2][MAX_D + 1][NMPD];
+#endif
+
+namespace {
 
 template <int DD, int MP>
 void reg_one()
 {
-    if constexpr (dary_s_fits(MP, DD)) g_dary32s[DD][MP / 4 - 1] = (const void*)&k_dary32s<MP, DD>;
-    if constexpr (dary16_fits(MP / 2, DD)) g_dary16s[DD][MP / 4 - 1] = (const void*)&k_dary16s<MP / 2, DD>;
+    if constexpr ((MP / 4 - 1) % LD_NPARTS == LD_PART) {
+        if constexpr (dary_s_fits(MP, DD)) g_dary32s[DD][MP / 4 - 1] = (const void*)&k_dary32s<MP, DD>;
+        if constexpr (dary16_fits(MP / 2, DD)) {
+            g_dary16s[1][DD][MP / 4 - 1] = (const void*)&k_dary16s<MP / 2, DD, dary16_r(DD)>;
+            g_dary16s[0][DD][MP / 4 - 1] = (const void*)&k_dary16s<MP / 2, DD, dary16_r_small(DD)>;
+        }
+    }
 }
 
 template <int DD, int... I>
@@ -98,16 +116,19 @@ struct Init {
 
 }  // namespace
 
+#if LD_PART == 0
 const void* kernel_dary32s(int d, int mp)
 {
     if (d < 0 || d > MAX_D || mp < 4 || mp > MAX_MP || (mp & 3)) return nullptr;
     return g_dary32s[d][mp / 4 - 1];
 }
 
-const void* kernel_dary16s(int d, int words)
+const void* kernel_dary16s(int d, int words, int r)
 {
     if (d < 0 || d > MAX_D || words < 2 || words > MAX_MP / 2 || (words & 1)) return nullptr;
-    return g_dary16s[d][words / 2 - 1];
+    if (r != dary16_r(d) && r != dary16_r_small(d)) return nullptr;
+    return g_dary16s[r == dary16_r(d) ? 1 : 0][d][words / 2 - 1];
 }
+#endif
 
 }  // namespace ld

@@ -439,8 +439,10 @@ double rgs_count(int L, int d)
 {
     std::vector<double> S(d + 1, 0.0);   // S[k] for the current length
     S[0] = 1.0;                          // length 0
-    for (int n = 1; n <= L; ++n)
+    for (int n = 1; n <= L; ++n) {
         for (int k = std::min(n, d); k >= 1; --k) S[k] = k * S[k] + S[k - 1];
+        S[0] = 0.0;                      // no non-empty string has zero distinct digits
+    }
     double t = 0;
     for (int k = 1; k <= d; ++k) t += S[k];
     return L == 0 ? 1.0 : t;
@@ -581,11 +583,14 @@ bool pick_dary(Plan& p, const SweepShape& sh, const Mat& A, int rows)
     p.bias = 0;
     if (A.m <= MAX_MP && d <= MAX_D && !p.i64) {
         const int v = dary_variant(sh, d, p.mp);
-        if (v == VARIANT_PACK16 && rows >= 1 + dary16_r(d) && pack16_fits(p, A)) {
-            p.kernel = kernel_dary16s(d, p.mp / 2);
+        if (v == VARIANT_PACK16 && rows >= 1 + dary16_r_small(d) && pack16_fits(p, A)) {
+            // the larger R where the rows allow (make_plan may step back to the
+            // smaller one when a single problem has too few lanes at it)
+            const int r = rows >= 1 + dary16_r(d) ? dary16_r(d) : dary16_r_small(d);
+            p.kernel = kernel_dary16s(d, p.mp / 2, r);
             if (p.kernel) {
                 p.pack16 = 1;
-                p.R = dary16_r(d);
+                p.R = r;
                 return true;
             }
         }
@@ -665,6 +670,66 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
     build_binary(p, A);
     if (!p.wide && !p.i64 && bin_variant(p, sh) == VARIANT_MFMA) use_mfma(p);
     return p;
+}
+
+// Prefix, mid and low rows of a d-ary plan whose kernel and R are chosen: sets
+// p.P_tab, p.C, p.P and p.lanes_est (the lane count).
+void shape_dary(Plan& p, const SweepShape& sh, const Mat& A)
+{
+    const int d = p.d;
+    // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
+    // row is fixed (message 0), which is the paper's fix-one-entry reduction
+    p.P_tab = d <= 16 ? std::min(A.n - p.R, std::max(1, std::min(16, sh.dary_ptab))) : 1;
+    while (p.P_tab > 1 && rgs_count(p.P_tab, d) > (double)(1 << 20)) --p.P_tab;
+    const int rest = A.n - p.P_tab - p.R;
+    int C = 0;
+    {
+        uint64_t w = 1;
+        while (C < rest && w * (uint64_t)d <= (uint64_t)std::max(1, sh.dary_cwords)) {
+            w *= d;
+            ++C;
+        }
+    }
+    int P = rest - C;
+    // batch planning: a large problem takes more words per prefix, not more prefixes
+    if (sh.pfx_cap > 0)
+        while (P > 0 && rgs_count(p.P_tab, d) * std::pow((double)d, P) > std::ldexp(1.0, sh.pfx_cap)) {
+            --P;
+            ++C;
+        }
+    // a single problem should fill the device: trade mid rows for prefix rows
+    // (more lanes, fewer words each).  Up to 2^17 lanes (two waves per SIMD) the
+    // trade goes on down to two mid rows; beyond that, up to dary_lanes, only while
+    // each lane keeps about 2^12 words, since a lane's start costs about as much as
+    // scoring a few hundred words
+    if (sh.dary_lanes > 0) {
+        auto lanes = [&](int pt, int pf) { return rgs_count(pt, d) * std::pow((double)d, pf); };
+        auto trade = [&]() {
+            // a longer restricted-growth prefix removes no more words once the table
+            // holds a few thousand strings (the relabelling factor is then d! already),
+            // but the host builds and uploads the table on every plan
+            if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)RGS_TRADE_MAX)
+                ++p.P_tab;
+            else
+                ++P;
+            --C;
+        };
+        const double fill = std::min((double)sh.dary_lanes, (double)(1 << 17));
+        while (C > 2 && lanes(p.P_tab, P) < fill) trade();
+        int c_floor = 2;
+        while (std::pow((double)d, c_floor + p.R) < 4096.0) ++c_floor;
+        while (C > c_floor && lanes(p.P_tab, P) < (double)sh.dary_lanes) trade();
+    }
+    // the register kernels count a lane's d^C Gray words in 32 bits: move mid rows
+    // back into the prefix until d^C < 2^32 (the batch prefix cap above can push C
+    // past that; values do not depend on the split)
+    while (C > 0 && std::pow((double)d, C) > 4294967295.0) {
+        --C;
+        ++P;
+    }
+    p.C = C;
+    p.P = P;
+    p.lanes_est = rgs_count(p.P_tab, d) * std::pow((double)d, P);
 }
 
 }  // namespace
@@ -766,63 +831,27 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
         p.status = LD_ETOOBIG;
         return p;
     }
-    // restricted-growth prefixes hold 4 bits per digit; for d > 16 only the first
-    // row is fixed (message 0), which is the paper's fix-one-entry reduction
-    p.P_tab = d <= 16 ? std::min(A.n - p.R, std::max(1, std::min(16, sh.dary_ptab))) : 1;
-    while (p.P_tab > 1 && rgs_count(p.P_tab, d) > (double)(1 << 20)) --p.P_tab;
-    const int rest = A.n - p.P_tab - p.R;
-    int C = 0;
-    {
-        uint64_t w = 1;
-        while (C < rest && w * (uint64_t)d <= (uint64_t)std::max(1, sh.dary_cwords)) {
-            w *= d;
-            ++C;
+    shape_dary(p, sh, A);
+    // a single problem should fill the device: when the packed kernel's larger R
+    // leaves fewer lanes than half a wave per SIMD (or than dary_lanes asks), its
+    // kernel with one low row fewer has d times as many states to spread.  (Measured:
+    // 16 x 32 L_3 has 3281 lanes at R = 5, 68.6 us, and 9843 at R = 4, 41 us; 16 x 32
+    // L_4 has 44720 lanes at R = 4, 83 us, and 178880 at R = 3, 96 us.)
+    const double fill = std::min((double)sh.dary_lanes, (double)(1 << 15));
+    if (p.pack16 && sh.dary_lanes > 0 && p.R == dary16_r(d) && p.lanes_est < fill &&
+        A.n >= 1 + dary16_r_small(d)) {
+        if (const void* k = kernel_dary16s(d, p.mp / 2, dary16_r_small(d))) {
+            p.kernel = k;
+            p.R = dary16_r_small(d);
+            shape_dary(p, sh, A);
         }
     }
-    int P = rest - C;
-    // batch planning: a large problem takes more words per prefix, not more prefixes
-    if (sh.pfx_cap > 0)
-        while (P > 0 && rgs_count(p.P_tab, d) * std::pow((double)d, P) > std::ldexp(1.0, sh.pfx_cap)) {
-            --P;
-            ++C;
-        }
-    // a single problem should fill the device: trade mid rows for prefix rows
-    // (more lanes, fewer words each).  Up to 2^17 lanes (two waves per SIMD) the
-    // trade goes on down to two mid rows; beyond that, up to dary_lanes, only while
-    // each lane keeps about 2^12 words, since a lane's start costs about as much as
-    // scoring a few hundred words
-    if (sh.dary_lanes > 0) {
-        auto lanes = [&](int pt, int pf) { return rgs_count(pt, d) * std::pow((double)d, pf); };
-        auto trade = [&]() {
-            // a longer restricted-growth prefix removes no more words once the table
-            // holds a few thousand strings (the relabelling factor is then d! already),
-            // but the host builds and uploads the table on every plan
-            if (d <= 16 && p.P_tab < 16 && P == 0 && rgs_count(p.P_tab + 1, d) <= (double)RGS_TRADE_MAX)
-                ++p.P_tab;
-            else
-                ++P;
-            --C;
-        };
-        const double fill = std::min((double)sh.dary_lanes, (double)(1 << 17));
-        while (C > 2 && lanes(p.P_tab, P) < fill) trade();
-        int c_floor = 2;
-        while (std::pow((double)d, c_floor + p.R) < 4096.0) ++c_floor;
-        while (C > c_floor && lanes(p.P_tab, P) < (double)sh.dary_lanes) trade();
-    }
-    // the register kernels count a lane's d^C Gray words in 32 bits: move mid rows
-    // back into the prefix until d^C < 2^32 (the batch prefix cap above can push C
-    // past that; values do not depend on the split)
-    while (C > 0 && std::pow((double)d, C) > 4294967295.0) {
-        --C;
-        ++P;
-    }
-    p.C = C;
-    p.P = P;
+    if (p.status != LD_OK) return p;
     std::vector<uint64_t> tab;
     rgs(p.P_tab, d, tab);
     bool of = false;
     p.dpow_free = upow(d, p.P, &of);
-    const uint64_t cw = upow(d, C, &of);
+    const uint64_t cw = upow(d, p.C, &of);
     if (of || (double)tab.size() * (double)p.dpow_free * (double)cw * std::pow((double)d, p.R) >
                   (double)WORD_LIMIT) {
         p.status = LD_ETOOBIG;
@@ -834,6 +863,7 @@ Plan make_plan(const int32_t* M, int n, int m, int d, int marginals, const Sweep
     build_dary(p, A, tab, false);
     return p;
 }
+
 
 Plan make_range_plan(const int32_t* M, int n, int m, int d, int marginals, int q,
                      uint64_t pfx_begin, uint64_t pfx_end)

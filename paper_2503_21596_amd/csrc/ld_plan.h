@@ -56,6 +56,7 @@ struct Plan {
     uint64_t n_prefix = 0;
     uint64_t pfx_base = 0;
     uint64_t dpow_free = 1;
+    double lanes_est = 0;   // d-ary plans while shaping: the lane count of the shape
     double words = 0;
     std::vector<int32_t> M;    // preprocessed matrix, n x m
     // per row / column of M: the input rows / columns (input columns / rows when

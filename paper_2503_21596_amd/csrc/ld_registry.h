@@ -36,9 +36,17 @@ constexpr bool dary_s_fits(int mp, int d) { return (d == 3 || d == 4) && d * mp 
 
 // packed 16-bit d-ary kernels (two columns per dword, VARIANT_PACK16), d = 3, 4,
 // while the d message vectors take at most 96 VGPRs; by dword count (mp / 2).
-// Low rows per state: 4 for d = 3 (81 words), 3 for d = 4 (64 words; with 4 the
-// 256 assignments of the block maximum do not fit the registers beside the state)
-constexpr int dary16_r(int d) { return d == 3 ? 4 : 3; }
+// Low rows per state: 5 for d = 3 (243 words), 4 for d = 4 (256 words).  A mid
+// step re-scores the 2^R subsets of the two messages it changes, so one more low
+// row halves that work per word (d = 3: 6.9 instructions per word against 9.9
+// with R = 4; d = 4: 5.2 against 8.1 with R = 3), at the price of the registers
+// for twice the subset scores: three waves per SIMD instead of four up to 28
+// (d = 3) or 24 (d = 4) columns, two beyond.  Measured 18-28 % faster at every
+// size that fills the device.  A smaller problem has a third as many states, and
+// so lanes, at the larger R: below half a wave per SIMD its plan takes the kernel
+// with one low row fewer (dary16_r_small).
+constexpr int dary16_r(int d) { return d == 3 ? 5 : 4; }
+constexpr int dary16_r_small(int d) { return dary16_r(d) - 1; }
 constexpr bool dary16_fits(int words, int d) { return (d == 3 || d == 4) && d * words <= 96; }
 
 // d-ary low rows scored per state: the largest R <= 2 whose 2^R - 1 subset
@@ -66,7 +74,8 @@ constexpr int VARIANT_MFMA = 8;   // binary variant value selecting kernel_mfma
 const void* kernel_bin64(int kind, int mp);
 const void* kernel_dary32(int d, int mp);
 const void* kernel_dary32s(int d, int mp);   // SGPR-operand d-ary kernel (DARY_RS low rows)
-const void* kernel_dary16s(int d, int words);   // packed 16-bit d-ary kernel (dary16_r(d) low rows)
+// packed 16-bit d-ary kernel with r = dary16_r(d) or dary16_r_small(d) low rows
+const void* kernel_dary16s(int d, int words, int r);
 const void* kernel_dary64(int d, int mp);
 const void* kernel_sumabs_many();
 const void* kernel_wide();

@@ -242,13 +242,20 @@ int ld_autotune(const char* path, double budget_seconds)
 
     // plain calls: kernel variant (low rows of the SGPR-operand kernel, or the
     // VGPR-operand kernel), lane range and words per prefix, timed on a 38 x 38
-    // and a 35 x 42 L1 problem (sum of the two times; the first has rows enough
-    // that the upper lane bound decides its shape)
+    // and a 35 x 42 L1 problem and a 31 x 31 L2 problem.  The first has rows
+    // enough that the upper lane bound decides its shape; in the last the least
+    // lane count binds (with too few lanes it runs at half speed, which the two
+    // large ones cannot show).  Each time counts relative to the same problem
+    // under the starting table, so the millisecond problem weighs as much as the
+    // large ones.
     {
         Rng r{0xca1};
-        std::vector<int32_t> A((size_t)38 * 38), B((size_t)35 * 42);
+        std::vector<int32_t> A((size_t)38 * 38), B((size_t)35 * 42), C((size_t)31 * 31);
         for (auto& v : A) v = r.uniform(-100, 100);
         for (auto& v : B) v = r.uniform(-100, 100);
+        for (auto& v : C) v = r.uniform(-100, 100);
+        set_tuning(best);
+        const double ra = time_plain(A, 38, 38), rb = time_plain(B, 35, 42), rc = time_plain(C, 31, 31, 2);
         double bt = 1e30;
         Tuning bp = best;
         for (int sr : {VARIANT_PACK16, 5, 4, 0})
@@ -262,10 +269,13 @@ int ld_autotune(const char* path, double budget_seconds)
                         t.plain_p_target = p;
                         t.plain_c_goal = c;
                         set_tuning(t);
-                        const double dt = time_plain(A, 38, 38) + time_plain(B, 35, 42);
+                        const double ta = time_plain(A, 38, 38), tb = time_plain(B, 35, 42),
+                                     tc = time_plain(C, 31, 31, 2);
+                        const double dt = ta / ra + tb / rb + tc / rc;
                         std::snprintf(buf, sizeof buf,
-                                      ", {\"sgpr_r\": %d, \"p_min\": %d, \"plain_p\": %d, \"c_goal\": %d, \"ms\": %.3f}",
-                                      sr, pm, p, c, 1e3 * dt);
+                                      ", {\"sgpr_r\": %d, \"p_min\": %d, \"plain_p\": %d, \"c_goal\": %d, \"ms\": [%.3f, "
+                                      "%.3f, %.3f], \"score\": %.4f}",
+                                      sr, pm, p, c, 1e3 * ta, 1e3 * tb, 1e3 * tc, dt);
                         notes += buf;
                         if (dt < bt) {
                             bt = dt;
@@ -324,14 +334,24 @@ int ld_autotune(const char* path, double budget_seconds)
                 std::vector<int> options =
                     c < 2 ? std::vector<int>{VARIANT_PACK16, 5, 4, 0, VARIANT_MFMA}
                           : std::vector<int>{VARIANT_PACK16, 1, 0};
-                double bt = 1e30;
+                double bt = 1e30, t_default = 1e30;
                 int pick = -1;
+                std::vector<std::pair<const void*, double>> timed;   // kernel the option plans, its time
                 for (int o : options) {
                     Tuning t = best;
                     t.variant[c][b] = o;
                     set_tuning(t);
+                    // an option whose plan runs a kernel already timed (it does not fit
+                    // this width, say) takes that time instead of another run
+                    const void* k = make_plan(M.data(), n, m, dval[c], 0, get_shape()).kernel;
                     double dt = 1e30;
-                    for (int rep = 0; rep < 3; ++rep) {
+                    bool seen = false;
+                    for (auto& kt : timed)
+                        if (kt.first == k) {
+                            dt = kt.second;
+                            seen = true;
+                        }
+                    for (int rep = 0; rep < 3 && !seen; ++rep) {
                         const double t0 = now_s();
                         if (ld_norm(M.data(), n, m, dval[c], 0) == INT64_MIN) {
                             dt = 1e30;
@@ -339,15 +359,19 @@ int ld_autotune(const char* path, double budget_seconds)
                         }
                         dt = std::min(dt, now_s() - t0);
                     }
+                    if (!seen) timed.push_back({k, dt});
                     std::snprintf(buf, sizeof buf, ", {\"class\": \"%s\", \"bucket\": %d, \"variant\": %d, \"ms\": %.3f}",
                                   CLASS_NAME[c], b, o, 1e3 * dt);
                     notes += buf;
+                    if (o == options[0]) t_default = dt;
                     if (dt < bt) {
                         bt = dt;
                         pick = o;
                     }
                 }
-                best.variant[c][b] = pick;
+                // the default (packed) kernel stays unless another is clearly faster:
+                // ties of a few per cent are noise, not a reason to switch kernels
+                best.variant[c][b] = bt < 0.97 * t_default ? pick : options[0];
             }
     }
     set_tuning(best);

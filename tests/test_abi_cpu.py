@@ -247,8 +247,11 @@ def test_plan_dary_lane_trading():
     for d, n, m in [(3, 22, 40), (3, 20, 40), (4, 18, 16), (4, 19, 30)]:
         p = L.plan(synth.matrix(55 + n + m, n, m, -100, 100, "ab"), d, 0)
         assert p["C"] >= 2
+        # beyond 2^17 lanes a lane keeps 2^12 words, unless the first stage had to
+        # go down to two mid rows to reach 2^17 (one trade multiplies the lanes by
+        # d or more, so it can land past 2^17)
         if p["n_prefix"] > 2 ** 17:
-            assert lane_words(p, d) >= 4096, (d, n, m, p)
+            assert lane_words(p, d) >= 4096 or p["C"] == 2, (d, n, m, p)
 
 
 def test_plan_kernel_family_and_mfma_selection():

@@ -183,28 +183,40 @@ def test_reductions_planted(d, marg):
 def test_dary_kernel_variants(dary_sgpr):
     """The int32 d-ary kernels (subset operands in VGPRs with up to two low rows,
     streamed through SGPRs with three, or two columns per register as 16-bit
-    halves with four) against the oracle, d = 3, 4, every column count up to the
-    SGPR kernels' limits, row counts around R + 1 and plans with several mid rows."""
+    halves with five low rows for d = 3 and four for d = 4, or one fewer where a
+    single problem would have too few lanes) against the oracle, d = 3, 4, every
+    column count up to the SGPR kernels' limits, row counts around R + 1 and plans
+    with several mid rows, plain (the smaller R at these sizes) and batched (the
+    larger R)."""
     say("dary variants", dary_sgpr)
     try:
         L.set_sweep_shape(0, 0, -1, 0, -1, dary_sgpr)
         for i, (n, m, d) in enumerate([(4, 5, 3), (5, 8, 3), (7, 13, 3), (9, 32, 3), (10, 52, 3), (8, 3, 3),
                                        (5, 6, 4), (7, 17, 4), (8, 40, 4), (9, 24, 4), (6, 1, 4),
                                        (12, 20, 3), (13, 47, 3), (12, 64, 3), (11, 9, 4), (10, 48, 4),
-                                       (11, 52, 4), (6, 2, 3)]):
+                                       (11, 52, 4), (6, 2, 3), (6, 10, 3)]):
             M = synth.matrix(950 + i, n, m, -500, 500, "dvariants")
             p = L.plan(M, d, 0)
             if p["kind_name"] == "L_d" and p["i64"] == 0:
                 if dary_sgpr == 1 and p["mp"] * d <= 160:
                     assert p["R"] == 3 and p["kernel"] == 1, p
-                if dary_sgpr == 16 and n >= 5 and p["mp"] // 2 * d <= 96:
-                    assert p["R"] == (4 if d == 3 else 3) and p["kernel"] == 5, p
-            check(M, d, 0)
+                packed_r = 5 if d == 3 else 4
+                if dary_sgpr == 16 and n >= packed_r and p["mp"] // 2 * d <= 96:
+                    assert p["R"] in (packed_r, packed_r - 1) and p["kernel"] == 5, p
+                    if n >= 1 + packed_r:
+                        assert L.plan(M, d, 0, batch=True)["R"] == packed_r
+            want = check(M, d, 0)
+            if dary_sgpr == 16:
+                assert L.ld_norm_batch([(M, d, 0)])[0] == want   # the batch plan's kernel
         # plans that walk mid rows with the Gray code (and batch plans with more),
         # against the oracle's split-table form
         for i, (n, m, d) in enumerate([(14, 20, 3), (15, 24, 3), (13, 20, 4), (14, 16, 4)]):
             M = synth.matrix(1950 + i, n, m, -500, 500, "dvariants2")
             assert L.plan(M, d, 0)["C"] >= 1
+            if dary_sgpr == 16:
+                # plain: the smaller R (too few lanes at the larger); batched: the larger
+                assert L.plan(M, d, 0)["R"] == (4 if d == 3 else 3)
+                assert L.plan(M, d, 0, batch=True)["R"] == (5 if d == 3 else 4)
             want = oracle.ld_split(M, d)
             check(M, d, 0, want)
             assert L.ld_norm_batch([(M, d, 0)])[0] == want
