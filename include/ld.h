@@ -284,8 +284,9 @@ int32_t ld_gray_change(uint32_t d, uint64_t j, uint32_t* from, uint32_t* to);
  * and for L_marg column 0 at most 21844, else the SGPR kernel with 5 low rows
  * runs); dary_sgpr: 1 for the d-ary kernel with
  * SGPR operands (d = 3, 4, three low rows) where it is built, 0 for the VGPR one,
- * 16 for the packed 16-bit d-ary kernel (two columns per register; four low rows
- * for d = 3, three for d = 4; used under the same column bound as the binary one,
+ * 16 for the packed 16-bit d-ary kernel (two columns per register; five low rows
+ * for d = 3, four for d = 4, one fewer for a single problem that would have under
+ * 2^15 lanes at that count; used under the same column bound as the binary one,
  * else the SGPR-operand kernel runs).  The compiled defaults are 16 for both.
  * An explicit sgpr_r or dary_sgpr also replaces the autotuner's per-width choices
  * for those kinds.  Values never depend on the shape. */
