@@ -1,0 +1,65 @@
+"""The shipped tuning table (paper_2503_21596_amd/tuning_mi355x.json) agrees with the
+measurements it carries: every value the autotuner wrote is the winner of its own
+timed phase under the tuner's rules.  Host only: reads the JSON, runs nothing."""
+import json
+import os
+
+import pytest
+
+TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2503_21596_amd",
+                     "tuning_mi355x.json")
+
+
+@pytest.fixture(scope="module")
+def table():
+    if not os.path.exists(TABLE):
+        pytest.skip("no shipped tuning table")
+    return json.load(open(TABLE))
+
+
+def test_batch_shape_is_the_fastest_measured(table):
+    rows = [m for m in table["measured"] if "batch_c" in m]
+    assert rows
+    best = min(rows, key=lambda m: m["ms"])
+    assert (table["bin_c_target"], table["batch_pfx_cap"], table["item_words"]) == \
+        (best["batch_c"], best["pfx_cap"], best["item_words"])
+
+
+def test_batch_side_streams(table):
+    rows = [m for m in table["measured"] if "batch_side_streams" in m]
+    assert {m["batch_side_streams"] for m in rows} == {0, 1, 3}
+    best = min(rows, key=lambda m: m["ms"])
+    # the fastest measured count, or the starting one (3) when the batch-shape phase
+    # had already measured that configuration faster
+    assert table["batch_side_streams"] in (best["batch_side_streams"], 3)
+
+
+def test_plain_shape_has_the_best_score(table):
+    rows = [m for m in table["measured"] if "score" in m]
+    assert rows
+    best = min(rows, key=lambda m: m["score"])
+    assert (table["sgpr_r"], table["plain_p_min"], table["plain_p_target"], table["plain_c_goal"]) == \
+        (best["sgpr_r"], best["p_min"], best["plain_p"], best["c_goal"])
+    # three representatives each (two large L1 problems and a 31 x 31 L2)
+    assert all(len(m["ms"]) == 3 for m in rows)
+
+
+def test_dary_lanes_is_the_fastest_measured(table):
+    rows = [m for m in table["measured"] if "dary_lanes" in m]
+    assert rows
+    assert table["plain_dary_lanes"] == min(rows, key=lambda m: m["ms"])["dary_lanes"]
+
+
+@pytest.mark.parametrize("cls", ["l1", "l2", "d3", "d4"])
+def test_kernel_variants_keep_the_default_unless_clearly_faster(cls, table):
+    """The packed kernel (16) stays unless another variant was at least 3 % faster on
+    the cell's representative; then the fastest is chosen."""
+    for b in range(4):
+        rows = {m["variant"]: m["ms"] for m in table["measured"] if m.get("class") == cls and m.get("bucket") == b}
+        assert 16 in rows, (cls, b)
+        chosen = table["variant_%s_%d" % (cls, b)]
+        fastest = min(rows, key=rows.get)
+        if rows[fastest] < 0.97 * rows[16]:
+            assert chosen == fastest, (cls, b, rows)
+        else:
+            assert chosen == 16, (cls, b, rows)
