@@ -135,7 +135,7 @@ constexpr int NMP = MAX_MP / 2;   // mp = 2, 4, ..., 64
 const void* g_bin32[NMP][MAX_R + 1] = {};
 const void* g_bin32s[NMP][MAX_RS + 1] = {};
 const void* g_bin64[MAX_MP / 8] = {};
-const void* g_bin16s[MAX_MP / 2] = {};   // words 1 .. 32 (L1 and L2 only)
+const void* g_bin16s[2][MAX_MP / 2] = {};   // [PACK16_R_BIG?][words 1 .. 32] (L1 and L2 only)
 
 template <int MP, int R>
 void reg_one()
@@ -154,7 +154,13 @@ void reg_mp()
     g_bin32s[MP / 2 - 1][4] = (const void*)&k_bin32s<MP, LD_KIND, 4>;
     g_bin32s[MP / 2 - 1][5] = (const void*)&k_bin32s<MP, LD_KIND, 5>;
     // packed kernels by word count MP / 2 (L_marg plans use the L1 ones)
-    if constexpr (LD_KIND != KIND_MARG) g_bin16s[MP / 2 - 1] = (const void*)&k_bin16s<MP / 2, LD_KIND, PACK16_R>;
+    if constexpr (LD_KIND != KIND_MARG) {
+        g_bin16s[0][MP / 2 - 1] = (const void*)&k_bin16s<MP / 2, LD_KIND, PACK16_R>;
+        // the larger low-row count for L1 (and L_marg through it) only: no L2 workload
+        // has the mid rows that repay it, and its 2 x 64 operand streams double the build
+        if constexpr (LD_KIND == KIND_L1)
+            g_bin16s[1][MP / 2 - 1] = (const void*)&k_bin16s<MP / 2, LD_KIND, PACK16_R_BIG>;
+    }
 }
 
 template <int... I>
@@ -184,10 +190,10 @@ const void* LD_CAT(lookup_bin32s_kind, LD_KIND)(int mp, int R)
     return g_bin32s[mp / 2 - 1][R];
 }
 
-const void* LD_CAT(lookup_bin16s_kind, LD_KIND)(int words)
+const void* LD_CAT(lookup_bin16s_kind, LD_KIND)(int words, int r)
 {
-    if (words < 1 || words > MAX_MP / 2) return nullptr;
-    return g_bin16s[words - 1];
+    if (words < 1 || words > MAX_MP / 2 || (r != PACK16_R && r != PACK16_R_BIG)) return nullptr;
+    return g_bin16s[r == PACK16_R_BIG ? 1 : 0][words - 1];
 }
 
 const void* LD_CAT(lookup_bin64_kind, LD_KIND)(int mp)

@@ -278,8 +278,8 @@ const void* lookup_bin32_kind2(int mp, int R);
 const void* lookup_bin32s_kind0(int mp, int R);
 const void* lookup_bin32s_kind1(int mp, int R);
 const void* lookup_bin32s_kind2(int mp, int R);
-const void* lookup_bin16s_kind0(int words);
-const void* lookup_bin16s_kind2(int words);
+const void* lookup_bin16s_kind0(int words, int r);
+const void* lookup_bin16s_kind2(int words, int r);
 const void* lookup_mfma_kind0(int mp);
 const void* lookup_mfma_kind1(int mp);
 const void* lookup_mfma_kind2(int mp);
@@ -307,12 +307,12 @@ const void* kernel_bin32s(int kind, int mp, int R)
     }
 }
 
-const void* kernel_bin16s(int kind, int words)
+const void* kernel_bin16s(int kind, int words, int r)
 {
     switch (kind) {
     case KIND_L1:
-    case KIND_MARG: return lookup_bin16s_kind0(words);
-    case KIND_L2: return lookup_bin16s_kind2(words);
+    case KIND_MARG: return lookup_bin16s_kind0(words, r);
+    case KIND_L2: return lookup_bin16s_kind2(words, r);
     default: return nullptr;
     }
 }

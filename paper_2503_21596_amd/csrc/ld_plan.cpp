@@ -549,7 +549,8 @@ void pick_bin32(Plan& p, const SweepShape& sh, Mat const& A)
     int sr = bin_variant(p, sh);
     if (sr == VARIANT_PACK16) {
         p.bias = 0;
-        const void* k = pack16_fits(p, A) ? kernel_bin16s(p.kind == PK_L2 ? KIND_L2 : KIND_L1, p.mp / 2) : nullptr;
+        const void* k =
+            pack16_fits(p, A) ? kernel_bin16s(p.kind == PK_L2 ? KIND_L2 : KIND_L1, p.mp / 2, PACK16_R) : nullptr;
         if (k) {
             p.kernel = k;
             p.pack16 = 1;
@@ -662,6 +663,15 @@ Plan finish_binary(Plan p, Mat A, const SweepShape& sh)
         A.n += 1;
     }
     choose_binary_shape(p, sh, A.n - 1);
+    // a plain call of a large problem (many mid rows per lane) takes the packed
+    // kernel with one more low row: the same prefixes, one mid row fewer
+    if (p.pack16 && sh.c_target == 0 && sh.big_r_c > 0 && p.C >= sh.big_r_c) {
+        if (const void* k = kernel_bin16s(p.kind == PK_L2 ? KIND_L2 : KIND_L1, p.mp / 2, PACK16_R_BIG)) {
+            p.kernel = k;
+            p.R = PACK16_R_BIG;
+            choose_binary_shape(p, sh, A.n - 1);
+        }
+    }
     if (p.wide && p.C > 40) {
         p.status = LD_ETOOBIG;
         return p;

@@ -62,11 +62,16 @@ constexpr int dary_r(int mp, int d)
 const void* kernel_bin32(int kind, int mp, int R);
 const void* kernel_bin32s(int kind, int mp, int R);
 // packed 16-bit kernel (two columns per dword; L1 and, through it, L_marg, and L2),
-// by dword count; PACK16_R low rows
+// by dword count; PACK16_R low rows, or (L1 and L_marg) PACK16_R_BIG for a plain
+// call of a large problem (one row update per 64 words instead of 32; with its operands it holds
+// four waves per SIMD instead of five, which only problems with many mid rows per
+// lane repay: 42 x 42 L1 1.267 -> 1.252 s, but 36 x 36 L1 17.8 -> 18.1 ms and the
+// batch and served workloads slower)
 constexpr int PACK16_R = 5;
+constexpr int PACK16_R_BIG = 6;
 constexpr int VARIANT_PACK16 = 16;   // binary variant value selecting kernel_bin16s
 constexpr int64_t PACK16_BOUND = 32767;   // largest sum_x |M_xy| of a column it takes
-const void* kernel_bin16s(int kind, int words);
+const void* kernel_bin16s(int kind, int words, int r);
 // int8-MFMA state-update kernel (binary kinds, int32, R = 5, C <= 16)
 const void* kernel_mfma(int kind, int mp);
 constexpr int MFMA_MAX_C = 16;

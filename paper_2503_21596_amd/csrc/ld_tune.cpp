@@ -109,11 +109,11 @@ bool write_tuning(const char* path, const Tuning& t, const std::string& notes)
                  "  \"bin_c_target\": %d,\n  \"dary_cwords\": %d,\n  \"item_words\": %.0f,\n"
                  "  \"batch_pfx_cap\": %d,\n  \"plain_p_target\": %d,\n  \"plain_c_goal\": %d,\n"
                  "  \"plain_r_drop\": %d,\n  \"sgpr_r\": %d,\n  \"dary_variant\": %d,\n"
-                 "  \"plain_p_min\": %d,\n  \"plain_dary_lanes\": %d,\n  \"batch_side_streams\": %d,\n"
-                 "  \"measured\": [%s]\n}\n",
+                 "  \"plain_p_min\": %d,\n  \"plain_dary_lanes\": %d,\n  \"plain_big_r_c\": %d,\n"
+                 "  \"batch_side_streams\": %d,\n  \"measured\": [%s]\n}\n",
                  t.bin_c_target, t.dary_cwords, t.item_words, t.batch_pfx_cap, t.plain_p_target, t.plain_c_goal,
-                 t.plain_r_drop, t.sgpr_r, t.dary_variant, t.plain_p_min, t.plain_dary_lanes, t.batch_side_streams,
-                 notes.c_str());
+                 t.plain_r_drop, t.sgpr_r, t.dary_variant, t.plain_p_min, t.plain_dary_lanes, t.plain_big_r_c,
+                 t.batch_side_streams, notes.c_str());
     std::fclose(f);
     return true;
 }
@@ -150,6 +150,7 @@ void set_tuning(const Tuning& t)
     s.sgpr_r = t.sgpr_r;
     s.dary_sgpr = t.dary_variant;
     s.dary_lanes = t.plain_dary_lanes;
+    s.big_r_c = t.plain_big_r_c;
     std::memcpy(s.variant, t.variant, sizeof s.variant);
     set_shape(s);
 }
@@ -241,21 +242,23 @@ int ld_autotune(const char* path, double budget_seconds)
     set_tuning(best);
 
     // plain calls: kernel variant (low rows of the SGPR-operand kernel, or the
-    // VGPR-operand kernel), lane range and words per prefix, timed on a 38 x 38
+    // VGPR-operand kernel), lane range and words per prefix, timed on a 40 x 40
     // and a 35 x 42 L1 problem and a 31 x 31 L2 problem.  The first has rows
-    // enough that the upper lane bound decides its shape; in the last the least
-    // lane count binds (with too few lanes it runs at half speed, which the two
-    // large ones cannot show).  Each time counts relative to the same problem
-    // under the starting table, so the millisecond problem weighs as much as the
-    // large ones.
+    // enough that the upper lane bound decides its shape, and few enough queue
+    // items per wave at the lower bounds that the end of the launch shows, as it
+    // does for larger problems (a 38 x 38 problem preferred 2^20 lanes, which cost
+    // a 42 x 42 one 3.5 %); in the last the least lane count binds (with too few
+    // lanes it runs at half speed, which the two large ones cannot show).  Each
+    // time counts relative to the same problem under the starting table, so the
+    // millisecond problem weighs as much as the large ones.
     {
         Rng r{0xca1};
-        std::vector<int32_t> A((size_t)38 * 38), B((size_t)35 * 42), C((size_t)31 * 31);
+        std::vector<int32_t> A((size_t)40 * 40), B((size_t)35 * 42), C((size_t)31 * 31);
         for (auto& v : A) v = r.uniform(-100, 100);
         for (auto& v : B) v = r.uniform(-100, 100);
         for (auto& v : C) v = r.uniform(-100, 100);
         set_tuning(best);
-        const double ra = time_plain(A, 38, 38), rb = time_plain(B, 35, 42), rc = time_plain(C, 31, 31, 2);
+        const double ra = time_plain(A, 40, 40), rb = time_plain(B, 35, 42), rc = time_plain(C, 31, 31, 2);
         double bt = 1e30;
         Tuning bp = best;
         for (int sr : {VARIANT_PACK16, 5, 4, 0})
@@ -269,7 +272,7 @@ int ld_autotune(const char* path, double budget_seconds)
                         t.plain_p_target = p;
                         t.plain_c_goal = c;
                         set_tuning(t);
-                        const double ta = time_plain(A, 38, 38), tb = time_plain(B, 35, 42),
+                        const double ta = time_plain(A, 40, 40), tb = time_plain(B, 35, 42),
                                      tc = time_plain(C, 31, 31, 2);
                         const double dt = ta / ra + tb / rb + tc / rc;
                         std::snprintf(buf, sizeof buf,
@@ -360,7 +363,7 @@ int ld_autotune(const char* path, double budget_seconds)
                         dt = std::min(dt, now_s() - t0);
                     }
                     if (!seen) timed.push_back({k, dt});
-                    std::snprintf(buf, sizeof buf, ", {\"class\": \"%s\", \"bucket\": %d, \"variant\": %d, \"ms\": %.3f}",
+                    std::snprintf(buf, sizeof buf, ", {\"class\": \"%s\", \"bucket\": %d, \"variant\": %d, \"ms\": %.4f}",
                                   CLASS_NAME[c], b, o, 1e3 * dt);
                     notes += buf;
                     if (o == options[0]) t_default = dt;
@@ -410,6 +413,7 @@ int ld_load_tuning(const char* path)
         t.dary_variant = v == VARIANT_PACK16 ? VARIANT_PACK16 : v != 0 ? 1 : 0;
     if (read_key(text, "batch_side_streams", &v)) t.batch_side_streams = std::max(0, std::min(7, (int)v));
     if (read_key(text, "plain_dary_lanes", &v)) t.plain_dary_lanes = (int)std::max(0.0, std::min(v, 1073741824.0));
+    if (read_key(text, "plain_big_r_c", &v)) t.plain_big_r_c = (int)std::max(0.0, std::min(v, 31.0));
     for (int c = 0; c < 4; ++c)
         for (int b = 0; b < 4; ++b) {
             char key[32];

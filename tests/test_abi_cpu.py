@@ -256,16 +256,18 @@ def test_plan_dary_lane_trading():
 
 def test_plan_kernel_family_and_mfma_selection():
     """ld_plan_info.kernel names the sweep kernel: the headline takes the packed 16-bit
-    kernel (5); with variant 8 the int8-MFMA kernel (2) where the mid-row deltas fit
-    int8 and 1 <= C <= 16, else the SGPR-operand kernel with 5 low rows (1)."""
+    kernel (5, six low rows); with variant 8 the int8-MFMA kernel (2, five low rows)
+    where the mid-row deltas fit int8 and 1 <= C <= 16, else the SGPR-operand kernel
+    with 5 low rows (1)."""
     M = synth.config_42_l1(0)
     p = L.plan(M, 1, 0)
-    assert p["kernel"] == 5 and p["R"] == 5
-    c0 = p["C"]
+    assert p["kernel"] == 5 and p["R"] == 6
+    rc0 = p["R"] + p["C"]
     try:
         L.set_sweep_shape(0, 0, -1, 0, 8, -1)
         p = L.plan(M, 1, 0)
-        assert p["kernel"] == 2 and p["R"] == 5 and p["C"] == c0 and 1 <= c0 <= 16
+        # the same prefix rows, one low row fewer and one mid row more
+        assert p["kernel"] == 2 and p["R"] == 5 and p["R"] + p["C"] == rc0 and 1 <= p["C"] <= 16
         big = synth.matrix(4, 20, 20, -1000, 1000, "abi")      # deltas 2 * 1000 do not fit int8
         p = L.plan(big, 1, 0)
         assert p["kernel"] == 1 and p["R"] == 5
@@ -275,6 +277,25 @@ def test_plan_kernel_family_and_mfma_selection():
     finally:
         L.load_tuning(L.TUNING_PATH)
     assert L.plan(M, 1, 0)["kernel"] == 5
+
+
+def test_packed_binary_low_rows_by_size():
+    """The packed binary kernel scores five low rows, six for a plain L1 / L_marg call
+    with at least 13 mid rows at five (one row update per 64 words; the same
+    prefixes, one mid row fewer); L2 and batch plans keep five."""
+    for n in (30, 36, 40, 41, 42):
+        M = synth.matrix(7 + n, n, 40, -100, 100, "bigr")
+        for d, marg in ((1, 0), (1, 1), (2, 0)):
+            p = L.plan(M, d, marg)
+            if p["kernel"] != 5:
+                continue
+            rows = p["n"]                             # after preprocessing (L1 may transpose)
+            c5 = rows - 1 - 5 - p["P"]                # mid rows at five low rows
+            want = 6 if d == 1 and c5 >= 13 else 5
+            assert p["R"] == want and p["R"] + p["C"] + p["P"] == rows - 1, (n, d, marg, p)
+            assert L.plan(M, d, marg, batch=True)["R"] == 5
+    assert L.plan(synth.config_42_l1(0), 1, 0)["R"] == 6
+    assert L.plan(synth.config_42_marg(0), 1, 1)["R"] == 6
 
 
 def test_batch_plan_dary_step_count_fits_32_bits(tmp_path):
@@ -327,8 +348,9 @@ def _check_small_problem_shapes():
     assert p["C"] == 0 and p["P"] == 14, p
     p = L.plan(synth.matrix(3, 27, 27, -100, 100, "fill"), 1, 0)
     assert p["C"] == 4 and p["P"] == 17, p
+    # 42 x 42 L1: 16 mid rows at five low rows, so six low rows and 15 mid rows
     p = L.plan(synth.config_42_l1(0), 1, 0)
-    assert p["C"] == 16 and p["P"] == 20, p
+    assert p["R"] == 6 and p["C"] == 15 and p["P"] == 20, p
 
 
 def test_noalloc_refuses_images_beyond_its_array():

@@ -59,7 +59,11 @@ def test_kernel_variants_keep_the_default_unless_clearly_faster(cls, table):
         assert 16 in rows, (cls, b)
         chosen = table["variant_%s_%d" % (cls, b)]
         fastest = min(rows, key=rows.get)
-        if rows[fastest] < 0.97 * rows[16]:
+        # the file rounds the times (to 1 us, or 0.1 us): within 1 us of the 3 % line
+        # either choice is consistent with the unrounded times the tuner compared
+        if abs(rows[fastest] - 0.97 * rows[16]) <= 1e-3:
+            assert chosen in (fastest, 16), (cls, b, rows)
+        elif rows[fastest] < 0.97 * rows[16]:
             assert chosen == fastest, (cls, b, rows)
         else:
             assert chosen == 16, (cls, b, rows)
