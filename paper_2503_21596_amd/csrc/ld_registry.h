@@ -65,7 +65,7 @@ const void* kernel_bin32s(int kind, int mp, int R);
 // by dword count; PACK16_R low rows, or (L1 and L_marg) PACK16_R_BIG for a plain
 // call of a large problem (one row update per 64 words instead of 32; with its operands it holds
 // four waves per SIMD instead of five, which only problems with many mid rows per
-// lane repay: 42 x 42 L1 1.267 -> 1.252 s, but 36 x 36 L1 17.8 -> 18.1 ms and the
+// lane repay: 42 x 42 L1 1.267 -> 1.244 s, but 36 x 36 L1 17.8 -> 18.1 ms and the
 // batch and served workloads slower)
 constexpr int PACK16_R = 5;
 constexpr int PACK16_R_BIG = 6;
