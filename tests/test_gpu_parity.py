@@ -322,6 +322,32 @@ def test_packed_kernel_bounds():
         L.load_tuning(L.TUNING_PATH)
 
 
+def test_packed_six_low_rows(tmp_path):
+    """The packed kernel with six low rows (plain L1 / L_marg calls with many mid
+    rows; by default only 40-odd-row problems) against the oracle for 24 and 25 rows
+    at widths from 24 to 63 columns (12 to 32 dwords, odd column counts padded),
+    under a tuning table whose mid-row threshold is lowered to 1.  Fewer columns
+    than rows cannot reach it: L1 and L_marg put the smaller side in the rows."""
+    say("six low rows")
+    t = json.load(open(L.TUNING_PATH))
+    t.pop("measured", None)
+    t["plain_big_r_c"] = 1
+    path = tmp_path / "big_r.json"
+    path.write_text(json.dumps(t))
+    try:
+        L.load_tuning(str(path))
+        for i, (n, m) in enumerate([(24, 24), (25, 33), (24, 42), (24, 50), (24, 57), (24, 63)]):
+            M = synth.matrix(950 + i, n, m, -1000, 1000, "six")
+            for marg in (0, 1):
+                p = L.plan(M, 1, marg)
+                assert p["R"] == 6 and p["kernel"] == 5 and p["C"] >= 1, p
+                check(M, 1, marg)
+                if i == 1:
+                    check(-M.T.copy(), 1, marg)
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+
+
 # ---------------------------------------------------------------------------
 # the benchmark configurations
 
