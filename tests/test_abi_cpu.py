@@ -298,6 +298,27 @@ def test_packed_binary_low_rows_by_size():
     assert L.plan(synth.config_42_marg(0), 1, 1)["R"] == 6
 
 
+def test_big_r_threshold_from_the_tuning_table(tmp_path):
+    """`plain_big_r_c` of a loaded table moves the switch to six low rows: 0 turns it
+    off (the 42 x 42 solve plans five), 1 lets a 24 x 24 L1 problem with one mid row
+    take it; the row split stays whole either way."""
+    t = json.load(open(L.TUNING_PATH))
+    t.pop("measured", None)
+    M42, M24 = synth.config_42_l1(0), synth.matrix(5, 24, 24, -100, 100, "bigr")
+    try:
+        for c, want42, want24 in ((0, 5, 5), (1, 6, 6), (13, 6, 5)):
+            t["plain_big_r_c"] = c
+            path = tmp_path / ("t%d.json" % c)
+            path.write_text(json.dumps(t))
+            L.load_tuning(str(path))
+            p42, p24 = L.plan(M42, 1, 0), L.plan(M24, 1, 0)
+            assert (p42["R"], p24["R"]) == (want42, want24), (c, p42, p24)
+            for p in (p42, p24):
+                assert p["R"] + p["C"] + p["P"] == p["n"] - 1, p
+    finally:
+        L.load_tuning(L.TUNING_PATH)
+
+
 def test_batch_plan_dary_step_count_fits_32_bits(tmp_path):
     """The d-ary register kernels count a lane's d^C Gray words in 32 bits.  A batch
     prefix cap moves prefix rows into the Gray walk; the planner must still keep
