@@ -256,6 +256,46 @@ def bench_mfma_variant(L, synth, stream, default_ms, golden, tuning=""):
             "value": v, "matches_oracle": (v == golden) if golden is not None else None}
 
 
+def bench_low_rows(L, synth, stream, reps: int = 3):
+    """Kernel time of plain L1 solves of 36 .. 42 rows with five and with six low
+    rows scored per state (a tuning table whose plain_big_r_c is 0: never six, or 1:
+    six wherever a mid row is left), the measurement behind the mid-row count at
+    which plain calls switch to six."""
+    import tempfile
+    tuned = os.path.exists(L.TUNING_PATH) and os.environ.get("LD_TUNING", "1") != "0"
+    base = json.load(open(L.TUNING_PATH)) if tuned else {}
+    base.pop("measured", None)
+    out = {}
+    try:
+        for n in (36, 38, 39, 40, 41, 42):
+            M = synth.config_42_l1(0) if n == 42 else synth.matrix(91 + 2 * n, n, n, -100, 100, "prof")
+            row, vals = {}, set()
+            for c in (0, 1):
+                with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+                    json.dump(dict(base, plain_big_r_c=c), f)
+                L.load_tuning(f.name)
+                os.unlink(f.name)
+                h = L.Prepared(M, 1, 0)
+                vals.add(h.run(stream))
+                ks = []
+                for _ in range(reps):
+                    vals.add(h.run(stream))
+                    ks.append(h.kernel_ms())
+                p = h.plan()
+                h.close()
+                row["R%d" % p["R"]] = {"C": p["C"], "P": p["P"], "ms": min(ks)}
+            if len(vals) != 1:
+                raise RuntimeError("values differ between low-row counts: %s" % sorted(vals))
+            row["mid_rows_at_five"] = row["R5"]["C"]
+            row["six_over_five"] = row["R6"]["ms"] / row["R5"]["ms"]
+            out["L1_%dx%d" % (n, n)] = row
+            print("low rows", n, json.dumps(row), file=sys.stderr, flush=True)
+    finally:
+        if tuned:
+            L.load_tuning(L.TUNING_PATH)
+    return out
+
+
 def bench_sweep(L, synth, stream, reps: int = 3):
     """Kernel time of one solve against the number of lanes (prefixes, one per lane)
     and the resident waves per SIMD, for L1, L2, L_3 and L_4: the launch-shape
@@ -360,6 +400,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark, time one solve each of L1, L2, L_3 and L_4 across lane "
                          "counts and waves per SIMD and print the table as one JSON line")
+    ap.add_argument("--low-rows", action="store_true",
+                    help="instead of the benchmark, time plain L1 solves of 36 .. 42 rows with five and "
+                         "with six low rows per state and print the table as one JSON line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB on the GPU (a kernel of "
                          "known traffic, to scale the HBM counters of a profiler run)")
@@ -385,6 +428,9 @@ def main():
         L.set_sweep_shape(0, 0, -1, 0, kv if kv in (0, 4, 5, 8, 16) else -1, kv if kv in (0, 1, 16) else -1)
     if a.sweep:
         print(json.dumps({"sweep": bench_sweep(L, synth, stream)}), flush=True)
+        return
+    if a.low_rows:
+        print(json.dumps({"low_rows": bench_low_rows(L, synth, stream)}), flush=True)
         return
     if a.small:
         print(json.dumps({"other_configs": bench_small_configs(L, synth, stream)}), flush=True)

@@ -43,7 +43,7 @@ struct SweepShape {
                                // sign columns before planning (exact reductions)
     int pfx_cap = 0;           // > 0 (batch planning): at most about 2^pfx_cap prefixes per
                                // problem; larger problems get more words per prefix instead
-    int big_r_c = 13;          // plain calls of the packed binary kernel: at least this many mid
+    int big_r_c = 11;          // plain calls of the packed binary kernel: at least this many mid
                                // rows at PACK16_R switch it to PACK16_R_BIG low rows (0: never)
 };
 

@@ -19,7 +19,7 @@ struct Tuning {
     int dary_variant = 16;        // int32 d = 3, 4: 16 packed where it fits, 1 SGPR operands, 0 VGPR
     int plain_dary_lanes = 1 << 19;  // plain calls, d >= 3: trade mid rows for prefix rows until
                                      // this many lanes exist
-    int plain_big_r_c = 13;          // plain calls: mid rows at which the packed binary kernel
+    int plain_big_r_c = 11;          // plain calls: mid rows at which the packed binary kernel
                                      // takes one more low row (0: never)
     int batch_side_streams = 3;      // batches: launches fan out over this many extra streams
                                      // (inside the captured graph for batch handles; 0: one

@@ -281,7 +281,7 @@ def test_plan_kernel_family_and_mfma_selection():
 
 def test_packed_binary_low_rows_by_size():
     """The packed binary kernel scores five low rows, six for a plain L1 / L_marg call
-    with at least 13 mid rows at five (one row update per 64 words; the same
+    with at least 11 mid rows at five (one row update per 64 words; the same
     prefixes, one mid row fewer); L2 and batch plans keep five."""
     for n in (30, 36, 40, 41, 42):
         M = synth.matrix(7 + n, n, 40, -100, 100, "bigr")
@@ -291,7 +291,7 @@ def test_packed_binary_low_rows_by_size():
                 continue
             rows = p["n"]                             # after preprocessing (L1 may transpose)
             c5 = rows - 1 - 5 - p["P"]                # mid rows at five low rows
-            want = 6 if d == 1 and c5 >= 13 else 5
+            want = 6 if d == 1 and c5 >= 11 else 5
             assert p["R"] == want and p["R"] + p["C"] + p["P"] == rows - 1, (n, d, marg, p)
             assert L.plan(M, d, marg, batch=True)["R"] == 5
     assert L.plan(synth.config_42_l1(0), 1, 0)["R"] == 6
