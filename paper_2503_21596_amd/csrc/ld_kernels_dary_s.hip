@@ -65,10 +65,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_wave
     dary_s_queue<Dary32S<MP, DD, DARY_RS>>(q);
 }
 
+// At two waves per SIMD (d = 3, five low rows, 30 to 48 columns) enough registers
+// are free to re-score both changed messages from one stream of operand loads; with
+// three or four waves, or more columns, that would spill.
+template <int W, int DD, int R>
+constexpr bool dary16_paired()
+{
+    return DD == 3 && dary16_waves(W, DD, R) == 2 && W <= 24;
+}
+
 template <int W, int DD, int R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary16_waves(W, DD, R)))) void k_dary16s(QArgs q)
 {
-    dary_s_queue<Dary32S<W, DD, R, true>>(q);
+    dary_s_queue<Dary32S<W, DD, R, true, dary16_paired<W, DD, R>()>>(q);
 }
 
 #ifndef LD_PART

@@ -173,7 +173,7 @@ struct Dary32 {
 // columns of a dword.  It needs sum_x |M_xy| <= 2^15 - 1 for every column: then
 // every per-message column sum, with or without low rows added, lies in
 // (-2^15, 2^15), so no half ever carries into the other.
-template <int MP, int DD, int R, bool PK = false>
+template <int MP, int DD, int R, bool PK = false, bool PAIRED = false>
 struct Dary32S {
     static constexpr int NS = 1 << R;
     static constexpr int RS = (MP + 15) & ~15;
@@ -214,6 +214,42 @@ struct Dary32S {
             X[s0 + 1] = a[1];
             X[s0 + 2] = a[2];
             X[s0 + 3] = a[3];
+        });
+    }
+
+    // refresh of messages KA and KB together: each statement of operand loads serves
+    // both (half the scalar loads and waits of two refresh calls)
+    template <int KA, int KB>
+    __device__ static __forceinline__ void refresh_pair(const uint32_t (&g)[DD][MP], uint64_t ob,
+                                                        uint32_t (&X)[DD][NS])
+    {
+        static_for<NS / 4>([&](auto q) {
+            constexpr int s0 = 4 * q;
+            uint32_t a[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+            static_for<N8>([&](auto c) {
+                u32x8 o0, o1, o2, o3;
+                sload_4x8<(s0 * RS + 8 * c) * 4, ((s0 + 1) * RS + 8 * c) * 4, ((s0 + 2) * RS + 8 * c) * 4,
+                          ((s0 + 3) * RS + 8 * c) * 4>(ob, o0, o1, o2, o3);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    constexpr int y0 = 8 * c;
+                    if (y0 + j >= MP) continue;
+                    const uint32_t x = g[KA][y0 + j], z = g[KB][y0 + j];
+                    a[0] = sad(x, o0[j], a[0]);
+                    a[1] = sad(x, o1[j], a[1]);
+                    a[2] = sad(x, o2[j], a[2]);
+                    a[3] = sad(x, o3[j], a[3]);
+                    b[0] = sad(z, o0[j], b[0]);
+                    b[1] = sad(z, o1[j], b[1]);
+                    b[2] = sad(z, o2[j], b[2]);
+                    b[3] = sad(z, o3[j], b[3]);
+                }
+            });
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                X[KA][s0 + i] = a[i];
+                X[KB][s0 + i] = b[i];
+            }
         });
     }
 
@@ -291,12 +327,15 @@ struct Dary32S {
             uint32_t from, to;
             const uint32_t i = dgc_change<DD>(t, &from, &to);
             cptr<int32_t> row = mid + i * MP;
+            // PAIRED (d = 3 only): the two changed messages are one of three unordered
+            // pairs (from + to = 1, 2, 3), re-scored together
+            static_assert(!PAIRED || DD == 3, "pairs by from + to need d = 3");
 #pragma unroll
             for (int k = 0; k < DD; ++k) {
                 if ((uint32_t)k == from) {
 #pragma unroll
                     for (int y = 0; y < MP; ++y) g[k][y] -= (uint32_t)row[y];
-                    refresh(g[k], ob, X[k]);
+                    if constexpr (!PAIRED) refresh(g[k], ob, X[k]);
                 }
             }
 #pragma unroll
@@ -304,8 +343,17 @@ struct Dary32S {
                 if ((uint32_t)k == to) {
 #pragma unroll
                     for (int y = 0; y < MP; ++y) g[k][y] += (uint32_t)row[y];
-                    refresh(g[k], ob, X[k]);
+                    if constexpr (!PAIRED) refresh(g[k], ob, X[k]);
                 }
+            }
+            if constexpr (PAIRED) {
+                const uint32_t pair = from + to;
+                if (pair == 1u)
+                    refresh_pair<0, 1>(g, ob, X);
+                else if (pair == 2u)
+                    refresh_pair<0, 2>(g, ob, X);
+                else
+                    refresh_pair<1, 2>(g, ob, X);
             }
             best = max(best, block(X));
         }
