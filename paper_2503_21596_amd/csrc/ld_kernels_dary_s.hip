@@ -65,13 +65,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dary_s_wave
     dary_s_queue<Dary32S<MP, DD, DARY_RS>>(q);
 }
 
-// At two waves per SIMD (d = 3, five low rows, 30 to 48 columns) enough registers
-// are free to re-score both changed messages from one stream of operand loads; with
-// three or four waves, or more columns, that would spill.
+// At two waves per SIMD (d = 3, five low rows, more than 28 columns) enough
+// registers are free to re-score both changed messages from one stream of operand
+// loads; with three or four waves that would spill.
 template <int W, int DD, int R>
 constexpr bool dary16_paired()
 {
-    return DD == 3 && dary16_waves(W, DD, R) == 2 && W <= 24;
+    return DD == 3 && dary16_waves(W, DD, R) == 2;
 }
 
 template <int W, int DD, int R>

@@ -327,8 +327,9 @@ struct Dary32S {
             uint32_t from, to;
             const uint32_t i = dgc_change<DD>(t, &from, &to);
             cptr<int32_t> row = mid + i * MP;
-            // PAIRED (d = 3 only): the two changed messages are one of three unordered
-            // pairs (from + to = 1, 2, 3), re-scored together
+            // PAIRED (d = 3 only): the reflected code moves a digit by one, so the two
+            // changed messages are {0, 1} (from + to = 1) or {1, 2} (from + to = 3),
+            // re-scored together
             static_assert(!PAIRED || DD == 3, "pairs by from + to need d = 3");
 #pragma unroll
             for (int k = 0; k < DD; ++k) {
@@ -347,11 +348,8 @@ struct Dary32S {
                 }
             }
             if constexpr (PAIRED) {
-                const uint32_t pair = from + to;
-                if (pair == 1u)
+                if (from + to == 1u)
                     refresh_pair<0, 1>(g, ob, X);
-                else if (pair == 2u)
-                    refresh_pair<0, 2>(g, ob, X);
                 else
                     refresh_pair<1, 2>(g, ob, X);
             }
