@@ -63,7 +63,16 @@ def _mat(M):
 
 
 def _threads(t):
-    return t if t else (os.cpu_count() or 1)
+    """t, or the CPUs this process may run on (capped by OMP_NUM_THREADS when set): more
+    threads than that only time-slice."""
+    if t:
+        return t
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(omp))) if omp.isdigit() and int(omp) > 0 else max(1, n)
 
 
 def l1(M, threads: int = 0) -> int:
